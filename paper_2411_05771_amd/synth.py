@@ -1,0 +1,104 @@
+"""Seeded synthetic inputs shared by the HIP path's tests/benchmark and the oracle.
+
+This module holds none of the method's arithmetic: it only draws phantoms,
+angle lists, rotation angles and noise with numpy's PCG64 generator.  The
+paper's CT100 images (Sec. 4.1.1) are not available; random ellipse phantoms
+of the same kind of piecewise-constant structure stand in for them.
+
+Seeds used across the repository: phantoms 1000+i, sketches 2000,
+rotations 3000, noise 4000, arrivals 5000.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+SEED_PHANTOM = 1000
+SEED_SKETCH = 2000
+SEED_ROTATION = 3000
+SEED_NOISE = 4000
+SEED_ARRIVALS = 5000
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def ellipse_params(seed: int, n_min: int = 5, n_max: int = 10) -> np.ndarray:
+    """Draw 5-10 ellipses: rows (cx, cy, a, b, alpha, intensity).
+
+    Centres uniform in the disk of radius 0.8 (normalised [-1,1]^2 frame),
+    semi-axes U(0.05, 0.4), orientation U[0, pi), intensity U(0.1, 1).
+    """
+    g = rng(seed)
+    k = int(g.integers(n_min, n_max + 1))
+    r = 0.8 * np.sqrt(g.uniform(0.0, 1.0, k))
+    t = g.uniform(0.0, 2.0 * math.pi, k)
+    cx, cy = r * np.cos(t), r * np.sin(t)
+    a = g.uniform(0.05, 0.4, k)
+    b = g.uniform(0.05, 0.4, k)
+    alpha = g.uniform(0.0, math.pi, k)
+    inten = g.uniform(0.1, 1.0, k)
+    return np.stack([cx, cy, a, b, alpha, inten], axis=1)
+
+
+def ellipse_phantom(n: int, seed: int, dtype=np.float32) -> np.ndarray:
+    """Point-sample an ellipse phantom at pixel centres; overlaps add.
+
+    Pixel (i, j) sits at normalised ((j - (n-1)/2) / (n/2), (i - (n-1)/2) / (n/2)).
+    """
+    e = ellipse_params(seed)
+    c = (n - 1) / 2.0
+    coords = (np.arange(n, dtype=np.float64) - c) / (n / 2.0)
+    X, Y = np.meshgrid(coords, coords)   # X varies along columns (j), Y along rows (i)
+    img = np.zeros((n, n), dtype=np.float64)
+    for cx, cy, a, b, alpha, inten in e:
+        ca, sa = math.cos(alpha), math.sin(alpha)
+        dx, dy = X - cx, Y - cy
+        xr = ca * dx + sa * dy
+        yr = -sa * dx + ca * dy
+        img[(xr / a) ** 2 + (yr / b) ** 2 <= 1.0] += inten
+    return img.astype(dtype)
+
+
+def phantom_batch(n: int, batch: int, first: int = 0, dtype=np.float32) -> np.ndarray:
+    return np.stack([ellipse_phantom(n, SEED_PHANTOM + first + i, dtype) for i in range(batch)])
+
+
+def interleaved_sketch(n_angles: int, n_splits: int, k: int) -> np.ndarray:
+    """S_k of the N-way interleaved split: angles k, k+N, k+2N, ... (int32)."""
+    if not 0 <= k < n_splits:
+        raise ValueError("k out of range")
+    return np.arange(k, n_angles, n_splits, dtype=np.int32)
+
+
+def random_sketch(n_angles: int, m: int, seed: int = SEED_SKETCH) -> np.ndarray:
+    """A seeded random subset of m distinct angles, ascending (int32)."""
+    g = rng(seed)
+    return np.sort(g.choice(n_angles, size=m, replace=False)).astype(np.int32)
+
+
+def rotation_angles(copies: int, seed: int = SEED_ROTATION) -> np.ndarray:
+    """phi ~ U[0, 2 pi), float64."""
+    return rng(seed).uniform(0.0, 2.0 * math.pi, copies)
+
+
+def cos_sin(phi) -> np.ndarray:
+    """[C,2] table of (cos phi, sin phi) in float64."""
+    phi = np.asarray(phi, dtype=np.float64).reshape(-1)
+    return np.stack([np.cos(phi), np.sin(phi)], axis=1)
+
+
+def std_noise(shape, seed: int = SEED_NOISE) -> np.ndarray:
+    """Standard normal draws (float64) to be scaled by the caller."""
+    return rng(seed).standard_normal(shape)
+
+
+def add_relative_noise(y_clean: np.ndarray, z: np.ndarray, rel: float = 0.01) -> np.ndarray:
+    """y = y_clean + rel * max(y_clean) * z  (sigma = 0.01 * max)."""
+    return y_clean + rel * float(np.max(y_clean)) * z
+
+
+def uniform(shape, seed: int, lo: float = 0.0, hi: float = 1.0) -> np.ndarray:
+    return rng(seed).uniform(lo, hi, shape)
