@@ -1,0 +1,181 @@
+/*
+ * skei_ct.h -- C ABI of the MI355X (gfx950) sketched-EI CT operator library.
+ *
+ * The library evaluates the operators that every sketched equivariant-imaging
+ * (EI) loss evaluation applies (Xu, Li, Tang, arXiv 2411.05771):
+ *
+ *   A      discrete Radon transform of a 2-D parallel-beam CT scan
+ *          (Sec. 4.1.1; y ~ A x of Sec. 2.1), computed with Joseph's method;
+ *   A_S    the sketched operator S A of Sec. 3.1, where the sketch S selects
+ *          whole projection angles (the interleaved angle subsets of
+ *          Sec. 4.2.1) and is passed as a list of angle indices;
+ *   A^T    the exact transpose of A (and A_S^T = A^T S^T);
+ *   fbp    filtered backprojection, the stable approximation of A^dagger
+ *          named in Sec. 2.1 and Sec. 4.1.1, and fbp_S = (S A)^dagger ~
+ *          (pi/m) B_S H of Sec. 3.1 -- Ram-Lak filter H, pixel-driven
+ *          linear-interpolation backprojection B_S;
+ *   T_phi  the image rotations that form the transformation group of
+ *          Sec. 4.1.3, by bilinear resampling;
+ *   the sketched test-time EI loss of Eq. (skeilossttt) / Algorithm 2 with
+ *   the reconstruction network taken as the identity, and its gradient with
+ *   respect to the image.
+ *
+ * Geometry (fixed by this library; the paper states none of it).  Image
+ * pixel (i, j) has centre X = j - (N-1)/2, Y = i - (N-1)/2 (row i <-> Y);
+ * detector k sits at s_k = k - (N_det-1)/2 with unit spacing; full-scan
+ * angle a is theta_a = a*pi/N_theta; ray (a, k) is {X cos + Y sin = s_k}.
+ *
+ * Conventions shared by every call:
+ *   - Arrays are caller-owned, contiguous, row-major DEVICE memory on the
+ *     device that was current when the geometry was created: float32 data,
+ *     int32 angle lists.  Images are [batch][N][N]; sinograms are
+ *     [batch][m][N_det] with row r holding angle angle_idx[r].
+ *   - Angle lists hold indices into the full scan, each in [0, N_theta);
+ *     repeats are allowed and rows follow list order.  Entries are NOT
+ *     checked on the device: an out-of-range entry is undefined behaviour
+ *     (the Python layer validates lists when it builds them).
+ *   - Outputs are overwritten, never accumulated.  Inputs and outputs must
+ *     not overlap.
+ *   - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is
+ *     the default stream).  No call synchronises the host.
+ *   - A skei_geom is immutable after creation; calls on different streams
+ *     may share it.
+ *   - Return value: SKEI_OK (0) or a negative SKEI_E* code; on error nothing
+ *     has been enqueued.  skei_strerror() gives the text.
+ *   - Results are deterministic: no atomics, fixed summation order, so the
+ *     same inputs give bitwise the same outputs whatever else is in flight.
+ */
+#ifndef SKEI_CT_H
+#define SKEI_CT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SKEI_OK = 0,
+    SKEI_EINVAL = -1,   /* null pointer, non-positive size, bad combination   */
+    SKEI_ENOMEM = -2,   /* device allocation failed (geometry / plans only)   */
+    SKEI_ELAUNCH = -3,  /* a HIP launch or runtime call failed                */
+    SKEI_ERANGE = -4,   /* size beyond what the kernels support               */
+    SKEI_ESPACE = -5    /* caller workspace smaller than the *_bytes() query  */
+};
+
+typedef struct skei_geom skei_geom;
+
+/* Library version string and error text (static storage). */
+const char *skei_version(void);
+const char *skei_strerror(int code);
+
+/* ------------------------------------------------------------------ */
+/* Geometry (Sec. 4.1.1: N x N image, N_theta uniformly spaced angles */
+/* in [0, pi), N_det unit-spaced detector bins).                      */
+/* Builds the per-angle table (cos, sin, Joseph stepping constants)   */
+/* in double precision on the host, rounds it once to float32 and     */
+/* uploads it, together with the Ram-Lak taps, to the current device. */
+/* Limits: 2 <= N <= 2032, 1 <= N_theta <= 65536, 2 <= N_det <= 2048.  */
+/* The returned object owns that device memory; destroy frees it.     */
+/* ------------------------------------------------------------------ */
+int skei_geom_create(int n, int n_angles, int n_det, skei_geom **out);
+int skei_geom_destroy(skei_geom *g);
+int skei_geom_info(const skei_geom *g, int *n, int *n_angles, int *n_det);
+
+/* y = A_S x   (Sec. 3.1 sketched forward operator; Joseph's method).
+ * x [batch][N][N] -> y [batch][m][N_det].  Row r is the Joseph line sum
+ * of every image along the rays of angle angle_idx[r]: step over the
+ * image rows (|cos| >= |sin|) or columns, interpolate linearly between the
+ * two nearest pixel centres and scale by the step length 1/max(|cos|,|sin|). */
+int skei_radon_fwd(const skei_geom *g, const float *x, int batch,
+                   const int32_t *angle_idx, int m, float *y, void *stream);
+
+/* x = A_S^T y   (exact transpose of skei_radon_fwd, computed per pixel as a
+ * gather over the m listed angles: no atomics).
+ * y [batch][m][N_det] -> x [batch][N][N]. */
+int skei_radon_adj(const skei_geom *g, const float *y, int batch,
+                   const int32_t *angle_idx, int m, float *x, void *stream);
+
+/* q = H p   (Ram-Lak filter, unit spacing: h(0)=1/4, h(odd n)=-1/(pi n)^2,
+ * h(even n)=0), a linear convolution along each detector row with zero
+ * padding, accumulated in double precision.  p, q: [rows][N_det]. */
+int skei_ramp(const skei_geom *g, const float *p, int rows, float *q, void *stream);
+
+/* x = B_S q   (pixel-driven backprojection without the pi/m factor: each
+ * pixel takes the linear interpolation of row r at its projection
+ * X cos + Y sin, zero off the detector, summed over the listed angles).
+ * q [batch][m][N_det] -> x [batch][N][N]. */
+int skei_backproject(const skei_geom *g, const float *q, int batch,
+                     const int32_t *angle_idx, int m, float *x, void *stream);
+
+/* q = B_S^T x   (exact transpose of skei_backproject, ray-driven gather).
+ * x [batch][N][N] -> q [batch][m][N_det]. */
+int skei_backproject_T(const skei_geom *g, const float *x, int batch,
+                       const int32_t *angle_idx, int m, float *q, void *stream);
+
+/* FBP as A^dagger (Sec. 2.1, Sec. 4.1.1) and its sketched form fbp_S of
+ * Sec. 3.1:  x = fbp_S y = (pi/m) B_S H y;   y' = fbp_S^T x = (pi/m) H B_S^T x.
+ * `work` is caller device scratch of at least skei_fbp_workspace_bytes()
+ * bytes (it holds the filtered sinogram); work_bytes is its size. */
+size_t skei_fbp_workspace_bytes(const skei_geom *g, int batch, int m);
+int skei_fbp(const skei_geom *g, const float *y, int batch, const int32_t *angle_idx, int m,
+             float *x, void *work, size_t work_bytes, void *stream);
+int skei_fbp_adj(const skei_geom *g, const float *x, int batch, const int32_t *angle_idx, int m,
+                 float *y, void *work, size_t work_bytes, void *stream);
+
+/* Rotations T_phi (Sec. 4.1.3 group of rotations), bilinear, zero fill:
+ *   out[b][c](p) = x[b](R(-phi_c) p)   about the image centre, i.e. the
+ *   output pixel at (X, Y) samples x at (cos X + sin Y, -sin X + cos Y).
+ * cos_sin: device float [copies][2] = (cos phi_c, sin phi_c).
+ * skei_rotate:     x [batch][N][N] -> out [batch][copies][N][N].
+ * skei_rotate_adj: h [batch][copies][N][N] -> g [batch][N][N],
+ *                  g[b] = sum_c T_{phi_c}^T h[b][c]  (exact transpose; gather). */
+int skei_rotate(const float *x, int batch, int copies, int n, const float *cos_sin,
+                float *out, void *stream);
+int skei_rotate_adj(const float *h, int batch, int copies, int n, const float *cos_sin,
+                    float *g, void *stream);
+
+/* Sum of squared differences  *out = sum_i (a_i - b_i)^2  (b may be NULL:
+ * sum a_i^2), reduced in double precision in a fixed order.  `out` is one
+ * device double.  `work` must hold skei_sumsq_workspace_bytes(len). */
+size_t skei_sumsq_workspace_bytes(size_t len);
+int skei_sumsq_diff(const float *a, const float *b, size_t len, double *out,
+                    void *work, size_t work_bytes, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Sketched test-time EI loss and gradient (Eq. skeilossttt, Alg. 2), */
+/* network = identity, for an image batch x [batch][N][N]:            */
+/*   r_MC[b]  = y[b][mc_idx] - A_mc x[b]                               */
+/*   z[b][c]  = T_c x[b],   r[b][c] = z[b][c] - fbp_S(A_S z[b][c])      */
+/*   loss     = sum_b ||r_MC[b]||^2 + (lambda/C) sum_{b,c} ||r[b][c]||^2 */
+/*   grad[b]  = -2 A_mc^T r_MC[b]                                       */
+/*              + (2 lambda / C) sum_c T_c^T (r[b][c] - A_S^T fbp_S^T r) */
+/* y is the full measured sinogram [batch][N_theta][N_det]; the MC     */
+/* term reads its rows mc_idx[0..m_mc) (all angles for the unsketched  */
+/* MC term, the sketch itself for Alg. 2's sketched MC term).          */
+/* loss: one device double.  grad: device [batch][N][N] or NULL (loss  */
+/* only).  `work`: skei_ei_workspace_bytes() bytes of device scratch.  */
+/* ------------------------------------------------------------------ */
+size_t skei_ei_workspace_bytes(const skei_geom *g, int batch, int m_mc, int m, int copies);
+int skei_ei_loss_grad(const skei_geom *g, const float *x, const float *y, int batch,
+                      const int32_t *mc_idx, int m_mc, const int32_t *angle_idx, int m,
+                      int copies, const float *cos_sin, float lambda,
+                      double *loss, float *grad, void *work, size_t work_bytes, void *stream);
+
+/* Profiling probe for skei_ei_loss_grad: when set, the next calls record
+ * hipEvent_t `ev_begin` / `ev_end` on their stream immediately before and
+ * after the launch of stage `stage` (SKEI_STAGE_*), so a caller can time one
+ * kernel inside the fused step with hipEventElapsedTime.  Pass stage < 0 (or
+ * null events) to clear.  Process-wide setting; not for concurrent callers. */
+enum {
+    SKEI_STAGE_ROTATE = 0, SKEI_STAGE_FWD_SKETCH = 1, SKEI_STAGE_RAMP = 2, SKEI_STAGE_BP_RESID = 3,
+    SKEI_STAGE_FWD_MC = 4, SKEI_STAGE_REDUCE = 5, SKEI_STAGE_BP_T = 6, SKEI_STAGE_RAMP_T = 7,
+    SKEI_STAGE_ADJ_SKETCH = 8, SKEI_STAGE_ADJ_MC = 9, SKEI_STAGE_ROTATE_ADJ = 10, SKEI_STAGE_COUNT = 11
+};
+int skei_probe_set(int stage, void *ev_begin, void *ev_end);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SKEI_CT_H */

@@ -1,0 +1,125 @@
+// Image rotations T_phi (the transformation group of Sec. 4.1.3) and their
+// exact transpose, both as gathers.
+//
+// T_phi: output pixel (X, Y) samples the input bilinearly at
+//   u = cos X + sin Y + cN (column),  v = -sin X + cos Y + cN (row),
+// zero outside.  The transpose is evaluated per input pixel p' by visiting the
+// output pixels whose sample point lies within one pixel of p' in both
+// coordinates -- a rotated 2 x 2 square, whose bounding box holds at most 3 x 3
+// pixel centres -- and recomputing each candidate's bilinear weight with
+// exactly the expressions of the forward kernel, so the two kernels apply
+// bitwise-identical matrix entries.
+#include <cmath>
+
+#include "skei_internal.h"
+
+namespace skei {
+namespace {
+
+struct Sample {
+    int i0, j0;
+    float au, av;
+};
+
+// The one place where a sample point and its bilinear fractions are computed.
+__device__ __forceinline__ Sample sample_point(int i, int j, float c, float s, float cN)
+{
+    const float X = (float)j - cN, Y = (float)i - cN;
+    const float u = fmaf(c, X, fmaf(s, Y, cN));
+    const float v = fmaf(-s, X, fmaf(c, Y, cN));
+    const float fu = floorf(u), fv = floorf(v);
+    Sample r;
+    r.j0 = (int)fu;
+    r.i0 = (int)fv;
+    r.au = u - fu;
+    r.av = v - fv;
+    return r;
+}
+
+__global__ void __launch_bounds__(256) k_rotate(const float *__restrict__ x, int n, int copies,
+                                                const float *__restrict__ cs, float *__restrict__ out)
+{
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    const int bc = blockIdx.y;                 // b * copies + c
+    if (p >= n * n) return;
+    const int b = bc / copies, c = bc - b * copies;
+    const int i = p / n, j = p - i * n;
+    const float cN = 0.5f * (float)(n - 1);
+    const Sample sp = sample_point(i, j, cs[2 * c], cs[2 * c + 1], cN);
+    const float *img = x + (size_t)b * n * n;
+    float acc = 0.0f;
+#pragma unroll
+    for (int di = 0; di < 2; di++) {
+        const int ii = sp.i0 + di;
+        const float wv = di ? sp.av : 1.0f - sp.av;
+#pragma unroll
+        for (int dj = 0; dj < 2; dj++) {
+            const int jj = sp.j0 + dj;
+            const float wu = dj ? sp.au : 1.0f - sp.au;
+            if (ii >= 0 && ii < n && jj >= 0 && jj < n) acc = fmaf(wv * wu, img[(size_t)ii * n + jj], acc);
+        }
+    }
+    out[(size_t)bc * n * n + p] = acc;
+}
+
+// g[b][p'] = alpha * sum_c sum_p T_c[p][p'] h[b][c][p] + beta * add[b][p']
+__global__ void __launch_bounds__(256) k_rotate_adj(const float *__restrict__ h, int n, int copies,
+                                                    const float *__restrict__ cs, float alpha,
+                                                    const float *__restrict__ add, float beta,
+                                                    float *__restrict__ g)
+{
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    const int b = blockIdx.y;
+    if (p >= n * n) return;
+    const int ip = p / n, jp = p - ip * n;
+    const float cN = 0.5f * (float)(n - 1);
+    const float Xp = (float)jp - cN, Yp = (float)ip - cN;
+    float acc = 0.0f;
+    for (int c = 0; c < copies; c++) {
+        const float co = cs[2 * c], si = cs[2 * c + 1];
+        const float* hc = h + ((size_t)b * copies + c) * n * n;
+        // centre of the candidate set: the output position whose sample is p'
+        const float colc = fmaf(co, Xp, fmaf(-si, Yp, cN));
+        const float rowc = fmaf(si, Xp, fmaf(co, Yp, cN));
+        const float hw = fabsf(co) + fabsf(si) + 1e-3f;
+        const int jlo = (int)ceilf(colc - hw), ilo = (int)ceilf(rowc - hw);
+#pragma unroll
+        for (int di = 0; di < 3; di++) {
+            const int i = ilo + di;
+            if (i < 0 || i >= n) continue;
+#pragma unroll
+            for (int dj = 0; dj < 3; dj++) {
+                const int j = jlo + dj;
+                if (j < 0 || j >= n) continue;
+                const Sample sp = sample_point(i, j, co, si, cN);
+                const int ei = ip - sp.i0, ej = jp - sp.j0;
+                if ((unsigned)ei > 1u || (unsigned)ej > 1u) continue;
+                const float wv = ei ? sp.av : 1.0f - sp.av;
+                const float wu = ej ? sp.au : 1.0f - sp.au;
+                acc = fmaf(wv * wu, hc[(size_t)i * n + j], acc);
+            }
+        }
+    }
+    float v = alpha * acc;
+    if (add) v = fmaf(beta, add[(size_t)b * n * n + p], v);
+    g[(size_t)b * n * n + p] = v;
+}
+
+}  // namespace
+
+int launch_rotate(const float *x, int batch, int copies, int n, const float *cs, float *out, hipStream_t st)
+{
+    const dim3 grid((n * n + 255) / 256, batch * copies);
+    hipLaunchKernelGGL(k_rotate, grid, dim3(256), 0, st, x, n, copies, cs, out);
+    return check_launch();
+}
+
+int launch_rotate_adj(const float *h, int batch, int copies, int n, const float *cs, float alpha,
+                      const float *add, float beta, float *g, hipStream_t st)
+{
+    const dim3 grid((n * n + 255) / 256, batch);
+    hipLaunchKernelGGL(k_rotate_adj, grid, dim3(256), 0, st, h, n, copies, cs, alpha, add, beta, g);
+    return check_launch();
+}
+
+}  // namespace skei

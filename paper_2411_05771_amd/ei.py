@@ -1,0 +1,102 @@
+"""Sketched test-time EI loss and gradient (Eq. skeilossttt, Algorithm 2).
+
+With the reconstruction network taken as the identity (the network, its
+weights and its optimiser are outside this library), one iteration of
+Algorithm 2 evaluates, for the current image estimate x:
+
+    r_MC   = y[mc] - A_mc x                              (MC term)
+    z_c    = T_c x,  r_c = z_c - fbp_S(A_S z_c)          (sketched EI term)
+    loss   = ||r_MC||^2 + (lambda / C) sum_c ||r_c||^2
+    grad   = -2 A_mc^T r_MC + (2 lambda / C) sum_c T_c^T (r_c - A_S^T fbp_S^T r_c)
+
+``EIStep`` runs this as one fused sequence of library kernels
+(``skei_ei_loss_grad``) with a reusable device workspace.  ``ei_loss_autograd``
+builds the same loss from the differentiable operators of ``ops`` so that
+torch.autograd differentiates it through the hand-written transposes.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import capi, ops
+
+
+class EIStep:
+    """Fused EI loss/gradient for a fixed geometry, batch and copy count.
+
+    y: full measured sinogram [B, N_theta, N_det] (device, float32).
+    The sketch, MC angle list and rotations may change between calls
+    (``set_sketch`` / ``set_rotations``) without reallocating.
+    """
+
+    def __init__(self, geom: ops.Geometry, y: torch.Tensor, sketch, cos_sin, lam: float = 1.0, mc=None):
+        self.geom = geom
+        y3 = y.unsqueeze(0) if y.dim() == 2 else y
+        ops._check(y3, torch.float32, geom.device, "y")
+        if tuple(y3.shape[1:]) != (geom.n_angles, geom.n_det):
+            raise ValueError("y must be the full sinogram [B, N_theta, N_det]")
+        self.y = y3
+        self.batch = y3.shape[0]
+        self.lam = float(lam)
+        self.sk = ops._as_sketch(geom, sketch)
+        self.mc = ops._as_sketch(geom, mc)
+        self.cs = cos_sin if isinstance(cos_sin, torch.Tensor) else ops.cos_sin_tensor(cos_sin, geom.device)
+        self.copies = self.cs.shape[0]
+        self._alloc()
+        self.loss = torch.zeros((), dtype=torch.float64, device=geom.device)
+
+    def _alloc(self):
+        nb = capi.query("skei_ei_workspace_bytes", self.geom.handle, self.batch, self.mc.m, self.sk.m, self.copies)
+        self._ws_bytes = int(nb)
+        self._ws = torch.empty(max(self._ws_bytes, 1), dtype=torch.uint8, device=self.geom.device)
+
+    def set_sketch(self, sketch):
+        sk = ops._as_sketch(self.geom, sketch)
+        grow = sk.m > self.sk.m
+        self.sk = sk
+        if grow:
+            self._alloc()
+
+    def set_rotations(self, cos_sin):
+        cs = cos_sin if isinstance(cos_sin, torch.Tensor) else ops.cos_sin_tensor(cos_sin, self.geom.device)
+        if cs.shape[0] != self.copies:
+            raise ValueError("copy count is fixed per EIStep")
+        self.cs = cs
+
+    def __call__(self, x: torch.Tensor, grad: torch.Tensor | None = None, want_grad: bool = True):
+        x3 = ops._img(self.geom, x)
+        if x3.shape[0] != self.batch:
+            raise ValueError("batch mismatch")
+        if want_grad and grad is None:
+            grad = torch.empty_like(x3)
+        capi.call("skei_ei_loss_grad", self.geom.handle, ops._ptr(x3), ops._ptr(self.y), self.batch,
+                  ops._ptr(self.mc.dev), self.mc.m, ops._ptr(self.sk.dev), self.sk.m, self.copies,
+                  ops._ptr(self.cs), ctypes.c_float(self.lam), ops._ptr(self.loss),
+                  ops._ptr(grad) if want_grad else None, ops._ptr(self._ws), self._ws_bytes, ops._stream())
+        if want_grad and x.dim() == 2:
+            grad = grad[0]
+        return self.loss, grad
+
+
+def ei_loss_autograd(x, y, geom: ops.Geometry, sketch, cos_sin, lam: float = 1.0, mc=None):
+    """The same loss assembled from the differentiable operators.
+
+    x: [B,N,N] (requires_grad as needed); y: [B,N_theta,N_det].  Row selection,
+    subtraction and the sums of squares are torch glue; every operator
+    (A_mc, T, A_S, fbp_S and their transposes in backward) is a library call.
+    """
+    sk = ops._as_sketch(geom, sketch)
+    mcs = ops._as_sketch(geom, mc)
+    cs = cos_sin if isinstance(cos_sin, torch.Tensor) else ops.cos_sin_tensor(cos_sin, geom.device)
+    x3 = x.unsqueeze(0) if x.dim() == 2 else x
+    y3 = y.unsqueeze(0) if y.dim() == 2 else y
+    b, n = x3.shape[0], geom.n
+    c = cs.shape[0]
+    r_mc = y3[:, torch.from_numpy(mcs.host.astype(np.int64)).to(y3.device)] - ops.radon_fwd(x3, geom, mcs)
+    z = ops.rotate(x3, cs).reshape(b * c, n, n)
+    w = ops.fbp(ops.radon_fwd(z, geom, sk), geom, sk)
+    r = z - w
+    return (r_mc.double() ** 2).sum() + (lam / c) * (r.double() ** 2).sum()
