@@ -55,10 +55,11 @@ EiSizes ei_sizes(const skei_geom *g, int batch, int m_mc, int m, int copies)
     s.img = bc * nn;
     s.sino = bc * (size_t)m * g->n_det;
     s.mc = (size_t)batch * m_mc * g->n_det;
-    s.part_mc = radon_fwd_partials(g, batch, m_mc);
+    s.part_mc = radon_fwd_partials(g, batch, m_mc, RayTune{});
     s.part_ei = gather_partials(g, (int)bc);
     s.total = align256(s.img * 4) * 2            // z (later d), r
-              + align256(s.sino * 4) * 2         // ys (later g1), qs (later g2)
+              + align256(s.sino * 8)             // ys (A_S z as float, later B_S^T r as double)
+              + align256(s.sino * 4)             // qs (H ys, later (pi/m) H B_S^T r)
               + align256(s.mc * 4)               // r_MC
               + align256(nn * batch * 4)         // A_mc^T r_MC
               + align256(s.part_mc * 8) + align256(s.part_ei * 8);
@@ -102,7 +103,7 @@ int skei_radon_fwd(const skei_geom *g, const float *x, int batch, const int32_t 
 {
     int rc = check_geom_op(g, x, batch, angle_idx, m, y);
     if (rc) return rc;
-    return launch_radon_fwd(g, x, batch, angle_idx, m, y, nullptr, nullptr, 0, S(stream));
+    return launch_radon_fwd(g, x, batch, angle_idx, m, y, nullptr, nullptr, RayTune{}, S(stream));
 }
 
 int skei_radon_adj(const skei_geom *g, const float *y, int batch, const int32_t *angle_idx, int m, float *x,
@@ -116,7 +117,7 @@ int skei_radon_adj(const skei_geom *g, const float *y, int batch, const int32_t 
 int skei_ramp(const skei_geom *g, const float *p, int rows, float *q, void *stream)
 {
     if (!g || !p || !q || rows <= 0) return SKEI_EINVAL;
-    return launch_ramp(g, p, rows, 1.0f, q, S(stream));
+    return launch_ramp(g, p, nullptr, rows, 1.0f, q, S(stream));
 }
 
 int skei_backproject(const skei_geom *g, const float *q, int batch, const int32_t *angle_idx, int m, float *x,
@@ -132,13 +133,15 @@ int skei_backproject_T(const skei_geom *g, const float *x, int batch, const int3
 {
     int rc = check_geom_op(g, x, batch, angle_idx, m, q);
     if (rc) return rc;
-    return launch_bp_T(g, x, batch, angle_idx, m, q, 0, S(stream));
+    return launch_bp_T(g, x, batch, angle_idx, m, q, nullptr, RayTune{}, S(stream));
 }
 
 size_t skei_fbp_workspace_bytes(const skei_geom *g, int batch, int m)
 {
     if (!g || batch <= 0 || m <= 0) return 0;
-    return align256((size_t)batch * m * g->n_det * sizeof(float));
+    // fbp keeps the filtered sinogram (float); fbp_adj keeps B_S^T x in double
+    // so that the high-pass ramp does not amplify its rounding
+    return align256((size_t)batch * m * g->n_det * sizeof(double));
 }
 
 int skei_fbp(const skei_geom *g, const float *y, int batch, const int32_t *angle_idx, int m, float *x, void *work,
@@ -149,7 +152,7 @@ int skei_fbp(const skei_geom *g, const float *y, int batch, const int32_t *angle
     if (!work) return SKEI_EINVAL;
     if (work_bytes < skei_fbp_workspace_bytes(g, batch, m)) return SKEI_ESPACE;
     float *q = static_cast<float *>(work);
-    rc = launch_ramp(g, y, batch * m, 1.0f, q, S(stream));
+    rc = launch_ramp(g, y, nullptr, batch * m, 1.0f, q, S(stream));
     if (rc) return rc;
     return launch_backproject(g, q, batch, angle_idx, m, (float)(kPi / m), x, nullptr, nullptr, S(stream));
 }
@@ -161,10 +164,10 @@ int skei_fbp_adj(const skei_geom *g, const float *x, int batch, const int32_t *a
     if (rc) return rc;
     if (!work) return SKEI_EINVAL;
     if (work_bytes < skei_fbp_workspace_bytes(g, batch, m)) return SKEI_ESPACE;
-    float *t = static_cast<float *>(work);
-    rc = launch_bp_T(g, x, batch, angle_idx, m, t, 0, S(stream));
+    double *t = static_cast<double *>(work);
+    rc = launch_bp_T(g, x, batch, angle_idx, m, nullptr, t, RayTune{}, S(stream));
     if (rc) return rc;
-    return launch_ramp(g, t, batch * m, (float)(kPi / m), y, S(stream));
+    return launch_ramp(g, nullptr, t, batch * m, (float)(kPi / m), y, S(stream));
 }
 
 int skei_rotate(const float *x, int batch, int copies, int n, const float *cos_sin, float *out, void *stream)
@@ -212,7 +215,8 @@ int skei_ei_loss_grad(const skei_geom *g, const float *x, const float *y, int ba
     Carver cv{static_cast<char *>(work), work_bytes};
     float *z = cv.take<float>(sz.img);
     float *r = cv.take<float>(sz.img);
-    float *ys = cv.take<float>(sz.sino);
+    double *ysd = cv.take<double>(sz.sino);
+    float *ys = reinterpret_cast<float *>(ysd);
     float *qs = cv.take<float>(sz.sino);
     float *rmc = cv.take<float>(sz.mc);
     float *amc = cv.take<float>((size_t)g->n * g->n * batch);
@@ -228,14 +232,14 @@ int skei_ei_loss_grad(const skei_geom *g, const float *x, const float *y, int ba
     if ((rc = staged(SKEI_STAGE_ROTATE, st, [&] { return launch_rotate(x, batch, copies, g->n, cos_sin, z, st); })))
         return rc;
     if ((rc = staged(SKEI_STAGE_FWD_SKETCH, st,
-                     [&] { return launch_radon_fwd(g, z, bc, angle_idx, m, ys, nullptr, nullptr, 0, st); })))
+                     [&] { return launch_radon_fwd(g, z, bc, angle_idx, m, ys, nullptr, nullptr, RayTune{}, st); })))
         return rc;
-    if ((rc = staged(SKEI_STAGE_RAMP, st, [&] { return launch_ramp(g, ys, bc * m, 1.0f, qs, st); }))) return rc;
+    if ((rc = staged(SKEI_STAGE_RAMP, st, [&] { return launch_ramp(g, ys, nullptr, bc * m, 1.0f, qs, st); }))) return rc;
     if ((rc = staged(SKEI_STAGE_BP_RESID, st,
                      [&] { return launch_backproject(g, qs, bc, angle_idx, m, pim, r, z, pei, st); })))
         return rc;
     if ((rc = staged(SKEI_STAGE_FWD_MC, st,
-                     [&] { return launch_radon_fwd(g, x, batch, mc_idx, m_mc, rmc, y, pmc, 0, st); })))
+                     [&] { return launch_radon_fwd(g, x, batch, mc_idx, m_mc, rmc, y, pmc, RayTune{}, st); })))
         return rc;
     if ((rc = staged(SKEI_STAGE_REDUCE, st, [&] {
              return launch_reduce2(pmc, sz.part_mc, 1.0, pei, sz.part_ei, (double)lambda / copies, loss, st);
@@ -244,9 +248,9 @@ int skei_ei_loss_grad(const skei_geom *g, const float *x, const float *y, int ba
     if (!grad) return SKEI_OK;
     // backward: ys = B_S^T r ; qs = (pi/m) H ys ; z = r - A_S^T qs ;
     //           amc = A_mc^T r_MC ; grad = (2 lambda / C) sum_c T_c^T z - 2 amc
-    if ((rc = staged(SKEI_STAGE_BP_T, st, [&] { return launch_bp_T(g, r, bc, angle_idx, m, ys, 0, st); })))
+    if ((rc = staged(SKEI_STAGE_BP_T, st, [&] { return launch_bp_T(g, r, bc, angle_idx, m, nullptr, ysd, RayTune{}, st); })))
         return rc;
-    if ((rc = staged(SKEI_STAGE_RAMP_T, st, [&] { return launch_ramp(g, ys, bc * m, pim, qs, st); }))) return rc;
+    if ((rc = staged(SKEI_STAGE_RAMP_T, st, [&] { return launch_ramp(g, nullptr, ysd, bc * m, pim, qs, st); }))) return rc;
     if ((rc = staged(SKEI_STAGE_ADJ_SKETCH, st,
                      [&] { return launch_radon_adj(g, qs, bc, angle_idx, m, z, r, st); })))
         return rc;

@@ -56,12 +56,17 @@ int skei_geom_create(int n, int n_angles, int n_det, skei_geom **out)
         const bool rows = 4 * a <= n_angles || 4 * a >= 3 * n_angles;
         const double cm = rows ? c : s, cM = rows ? s : c;
         skei::AngleRow r{};
+        const double base = -cD / cm + cN * (1.0 + cM / cm);
+        const double two32 = 4294967296.0;
+        r.base_fx = (int64_t)std::llround(base * two32);
+        r.inv_fx = (int64_t)std::llround(two32 / cm);
+        r.du_fx = (int64_t)std::llround(-cM / cm * two32);
         r.c = (float)c;
         r.s = (float)s;
         r.inv_m = (float)(1.0 / cm);
         r.du = (float)(-cM / cm);
-        r.base = (float)(-cD / cm + cN * (1.0 + cM / cm));
-        r.scale = (float)(1.0 / std::fabs(cm));
+        r.base = (float)base;
+        r.scale = 1.0 / std::fabs(cm);
         r.w = (float)std::fabs(cm);
         r.inv_w2 = (float)(1.0 / (cm * cm));
         r.rows = rows ? 1 : 0;

@@ -8,8 +8,8 @@
 // precision, Joseph weights) are staged beside it.  Each pixel then reads one
 // 8-byte LDS entry per angle: (value, next value) for the Joseph adjoint, or
 // (value, next - value) for the linear-interpolation backprojection.
-// Positions inside the tile are small numbers (tile-local coordinates), so the
-// float rounding of the interpolation position stays near 2e-6 px.
+// Positions are formed in double relative to the tile origin, so the
+// interpolation weights carry only their final float rounding.
 #include <cmath>
 
 #include "skei_internal.h"
@@ -25,25 +25,52 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-template <int KIND, int MODE>
-__global__ void __launch_bounds__(256) k_gather(const float *__restrict__ in, int n, int n_det,
-                                                const int32_t *__restrict__ idx, int m,
-                                                const AngleRow *__restrict__ tab, float scale,
-                                                float *__restrict__ out, const float *__restrict__ other,
-                                                double *__restrict__ partial)
+struct GatherAngle {
+    double c, s, t0;   // cos, sin, detector coordinate of the tile origin within the window
+    float w, wm1;      // Joseph width max(|cos|,|sin|) and w - 1
+};
+
+// XCD-major tile mapping (workgroup L runs on XCD L % 8): each XCD takes a
+// contiguous range of (image, tile) items, so an image's tiles share one L2.
+__device__ __forceinline__ bool decode_item(int total, int &item)
 {
-    __shared__ float4 prm[kAngleChunk];               // (cos, sin, window-local origin, w)
+    const int L = blockIdx.x;
+    const int per = (total + 7) >> 3;
+    const int pos = L >> 3;
+    item = (L & 7) * per + pos;
+    return pos < per && item < total;
+}
+
+// A workgroup holds a 16 x 16 tile x GA angle groups: thread (pixel, ga) sums
+// the listed angles r with r % GA == ga, and the GA partial sums are added in a
+// fixed order through LDS.  GA depends only on m, and positions are relative
+// to the fixed 16 x 16 tile grid, so every pixel's arithmetic is the same
+// whatever the batch size -- results are bitwise batch invariant.
+template <int KIND, int MODE, int GA>
+__global__ void __launch_bounds__(256 * GA) k_gather(const float *__restrict__ in, int n, int n_det,
+                                                     const int32_t *__restrict__ idx, int m,
+                                                     const AngleRow *__restrict__ tab, float scale,
+                                                     float *__restrict__ out, const float *__restrict__ other,
+                                                     double *__restrict__ partial, int total)
+{
+    constexpr int TILE = 16, NPIX = TILE * TILE, BS = NPIX * GA, WIN = 2 * TILE;
+    __shared__ GatherAngle prm[kAngleChunk];
     __shared__ int kst[kAngleChunk];                  // first detector of each window
     __shared__ float iw2[kAngleChunk];                // 1/w^2 (Joseph weights)
-    __shared__ float2 win[kAngleChunk * kWin];
-    __shared__ double red[4];
+    __shared__ float2 win[kAngleChunk * WIN];
+    __shared__ float part[GA][NPIX];
+    __shared__ double red[NPIX / 64];
 
-    const int tiles_x = (n + kTile - 1) / kTile;
-    const int tile = blockIdx.x, b = blockIdx.y;
-    const int i0 = (tile / tiles_x) * kTile, j0 = (tile % tiles_x) * kTile;
+    int item;
+    if (!decode_item(total, item)) return;
+    const int tiles_x = (n + TILE - 1) / TILE;
+    const int tiles = tiles_x * tiles_x;
+    const int b = item / tiles, tile = item - b * tiles;
+    const int i0 = (tile / tiles_x) * TILE, j0 = (tile % tiles_x) * TILE;
     const int tid = threadIdx.x;
-    const int dx = tid & (kTile - 1), dy = tid >> 4;
-    const float fdx = (float)dx, fdy = (float)dy;
+    const int px = tid % NPIX, ga = tid / NPIX;
+    const int dx = px % TILE, dy = px / TILE;
+    const double fdx = (double)dx, fdy = (double)dy;
     const double cN = 0.5 * (n - 1), cD = 0.5 * (n_det - 1);
     const float *src = in + (size_t)b * m * n_det;
 
@@ -51,41 +78,43 @@ __global__ void __launch_bounds__(256) k_gather(const float *__restrict__ in, in
     for (int A0 = 0; A0 < m; A0 += kAngleChunk) {
         const int Ac = min(kAngleChunk, m - A0);
         __syncthreads();
-        if (tid < Ac) {
-            const AngleRow t = tab[idx[A0 + tid]];
+        for (int a = tid; a < Ac; a += BS) {
+            const AngleRow t = tab[idx[A0 + a]];
             const double c = t.c, s = t.s;
             const double X0 = j0 - cN, Y0 = i0 - cN;
             const double org = X0 * c + Y0 * s + cD;
-            const double tmin = org + fmin(0.0, (kTile - 1) * c) + fmin(0.0, (kTile - 1) * s);
+            const double tmin = org + fmin(0.0, (TILE - 1) * c) + fmin(0.0, (TILE - 1) * s);
             const double k0 = floor(tmin) - 1.0;
-            prm[tid] = make_float4(t.c, t.s, (float)(org - k0), t.w);
-            kst[tid] = (int)k0;
-            iw2[tid] = t.inv_w2;
+            prm[a] = GatherAngle{c, s, org - k0, t.w, t.w - 1.0f};
+            kst[a] = (int)k0;
+            iw2[a] = t.inv_w2;
         }
         __syncthreads();
-        for (int e = tid; e < Ac * kWin; e += 256) {
-            const int a = e / kWin, wi = e % kWin;
+        for (int e = tid; e < Ac * WIN; e += BS) {
+            const int a = e / WIN, wi = e % WIN;
             const int k = kst[a] + wi;
             const float *row = src + (size_t)(A0 + a) * n_det;
             const float v0 = (k >= 0 && k < n_det) ? row[k] : 0.0f;
             const float v1 = (k + 1 >= 0 && k + 1 < n_det) ? row[k + 1] : 0.0f;
-            if (KIND == kJosephAdj) {
+            if (KIND == kJosephAdj)
                 win[e] = make_float2(v0 * iw2[a], v1 * iw2[a]);
-            } else {
+            else
                 win[e] = make_float2(v0, v1 - v0);
-            }
         }
         __syncthreads();
-        for (int a = 0; a < Ac; a++) {
-            const float4 p = prm[a];
-            const float tl = fmaf(fdx, p.x, fmaf(fdy, p.y, p.z));
-            const int k0 = (int)tl;                          // tl >= 1 by construction
-            const float f = tl - (float)k0;
-            const float2 e = win[a * kWin + k0];
+#pragma unroll 4
+        for (int a = ga; a < Ac; a += GA) {
+            const GatherAngle p = prm[a];
+            // window-local detector coordinate in double: exact to ~1e-15 px,
+            // at the same issue rate as float on this device
+            const double tl = fma(fdx, p.c, fma(fdy, p.s, p.t0));
+            const int k0 = (int)tl;                          // 1 <= tl < WIN - 1 by construction
+            const float f = (float)__builtin_amdgcn_fract(tl);
+            const float2 e = win[a * WIN + k0];
             if (KIND == kJosephAdj) {
                 // weights Lambda((k - t)/w)/w for k = k0, k0+1 (the 1/w^2 is in the window)
                 const float wa = fmaxf(p.w - f, 0.0f);
-                const float wb = fmaxf(f + (p.w - 1.0f), 0.0f);
+                const float wb = fmaxf(f + p.wm1, 0.0f);
                 acc = fmaf(wa, e.x, acc);
                 acc = fmaf(wb, e.y, acc);
             } else {
@@ -94,10 +123,18 @@ __global__ void __launch_bounds__(256) k_gather(const float *__restrict__ in, in
             }
         }
     }
+    if (GA > 1) {
+        part[ga][px] = acc;
+        __syncthreads();
+        acc = part[0][px];
+#pragma unroll
+        for (int g = 1; g < GA; g++) acc += part[g][px];
+    }
 
+    // the threads of angle group 0 write the tile
     const int i = i0 + dy, j = j0 + dx;
     double ss = 0.0;
-    if (i < n && j < n) {
+    if (ga == 0 && i < n && j < n) {
         const size_t o = ((size_t)b * n + i) * n + j;
         float v = acc * scale;
         if (MODE == kResidSub) {
@@ -108,37 +145,57 @@ __global__ void __launch_bounds__(256) k_gather(const float *__restrict__ in, in
     }
     if (MODE == kResidSub && partial) {
         ss = wave_sum(ss);
-        if ((tid & 63) == 0) red[tid >> 6] = ss;
+        if ((tid & 63) == 0 && tid < NPIX) red[tid >> 6] = ss;
         __syncthreads();
-        if (tid == 0) partial[(size_t)b * gridDim.x + tile] = red[0] + red[1] + red[2] + red[3];
+        if (tid == 0) {
+            double s = 0.0;
+            for (int w = 0; w < NPIX / 64; w++) s += red[w];
+            partial[item] = s;
+        }
     }
+}
+
+// Angle groups per pixel: a function of m only (never of the batch).
+int angle_groups(int m) { return m >= 256 ? 4 : m >= 64 ? 2 : 1; }
+
+template <int KIND, int GA>
+int gather_launch_g(const skei_geom *g, const float *in, int batch, const int32_t *idx, int m, float scale,
+                    float *out, const float *other, double *partial, hipStream_t st)
+{
+    const int n = g->n;
+    const long long tiles = (long long)((n + 15) / 16) * ((n + 15) / 16);
+    const long long total = tiles * batch;
+    if (total > 0x0fffffffLL) return SKEI_ERANGE;
+    const dim3 grid((unsigned)(8 * ((total + 7) / 8))), block(256 * GA);
+    if (other)
+        hipLaunchKernelGGL((k_gather<KIND, kResidSub, GA>), grid, block, 0, st, in, n, g->n_det, idx, m, g->tab,
+                           scale, out, other, partial, (int)total);
+    else
+        hipLaunchKernelGGL((k_gather<KIND, kPlain, GA>), grid, block, 0, st, in, n, g->n_det, idx, m, g->tab,
+                           scale, out, nullptr, nullptr, (int)total);
+    return check_launch();
 }
 
 template <int KIND>
 int gather_launch(const skei_geom *g, const float *in, int batch, const int32_t *idx, int m, float scale,
                   float *out, const float *other, double *partial, hipStream_t st)
 {
-    const int n = g->n;
-    const int tiles = ((n + kTile - 1) / kTile) * ((n + kTile - 1) / kTile);
-    const dim3 grid(tiles, batch);
-    if (other)
-        hipLaunchKernelGGL((k_gather<KIND, kResidSub>), grid, dim3(256), 0, st, in, n, g->n_det, idx, m, g->tab,
-                           scale, out, other, partial);
-    else
-        hipLaunchKernelGGL((k_gather<KIND, kPlain>), grid, dim3(256), 0, st, in, n, g->n_det, idx, m, g->tab,
-                           scale, out, nullptr, nullptr);
-    return check_launch();
+    switch (angle_groups(m)) {
+    case 4: return gather_launch_g<KIND, 4>(g, in, batch, idx, m, scale, out, other, partial, st);
+    case 2: return gather_launch_g<KIND, 2>(g, in, batch, idx, m, scale, out, other, partial, st);
+    default: return gather_launch_g<KIND, 1>(g, in, batch, idx, m, scale, out, other, partial, st);
+    }
 }
 
-// The window must hold the tile's projection span (< (kTile-1)*sqrt(2)) plus
-// the one-bin lead and the interpolation neighbour.
-static_assert(kWin >= 2 + 22 + 2, "detector window too small for the pixel tile");
+// The window must hold the tile's projection span (< 15*sqrt(2)) plus the
+// one-bin lead and the interpolation neighbour.
+static_assert(2 * 16 >= 2 + 22 + 2, "detector window too small for the pixel tile");
 
 }  // namespace
 
 size_t gather_partials(const skei_geom *g, int batch)
 {
-    const size_t t = (size_t)((g->n + kTile - 1) / kTile);
+    const size_t t = (size_t)((g->n + 15) / 16);
     return t * t * batch;
 }
 

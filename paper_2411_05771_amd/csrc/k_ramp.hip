@@ -12,19 +12,20 @@
 namespace skei {
 namespace {
 
-template <int RPT>
-__global__ void __launch_bounds__(256) k_ramp(const float *__restrict__ p, int n_det,
+template <int RPT, typename IN>
+__global__ void __launch_bounds__(256) k_ramp(const IN *__restrict__ p, int n_det,
                                               const double *__restrict__ hodd, float scale,
                                               float *__restrict__ q)
 {
-    extern __shared__ float row[];          // [pad | n_det values | pad], pad = n_det + 1
+    extern __shared__ __align__(16) unsigned char ramp_raw[];
+    IN *row = reinterpret_cast<IN *>(ramp_raw);   // [pad | n_det values | pad], pad = n_det + 1
     const int pad = n_det + 1;
     const int r = blockIdx.x;
     const int tid = threadIdx.x, bs = blockDim.x;
-    const float *src = p + (size_t)r * n_det;
+    const IN *src = p + (size_t)r * n_det;
     for (int e = tid; e < 3 * n_det + 2; e += bs) {
         const int j = e - pad;
-        row[e] = (j >= 0 && j < n_det) ? src[j] : 0.0f;
+        row[e] = (j >= 0 && j < n_det) ? src[j] : (IN)0;
     }
     __syncthreads();
 
@@ -41,8 +42,8 @@ __global__ void __launch_bounds__(256) k_ramp(const float *__restrict__ p, int n
 #pragma unroll
         for (int i = 0; i < RPT; i++) {
             const int k = min(tid + i * bs, n_det - 1);
-            const float pair = row[pad + k - d] + row[pad + k + d];
-            acc[i] = fma(h, (double)pair, acc[i]);
+            const double pair = (double)row[pad + k - d] + (double)row[pad + k + d];
+            acc[i] = fma(h, pair, acc[i]);
         }
     }
 #pragma unroll
@@ -52,20 +53,19 @@ __global__ void __launch_bounds__(256) k_ramp(const float *__restrict__ p, int n
     }
 }
 
-}  // namespace
-
-int launch_ramp(const skei_geom *g, const float *p, int rows, float scale, float *q, hipStream_t st)
+template <typename IN>
+int ramp_launch(const skei_geom *g, const IN *p, int rows, float scale, float *q, hipStream_t st)
 {
     const int n_det = g->n_det;
     const int rpt = (n_det + 255) / 256;
     const int per = (n_det + rpt - 1) / rpt;
     const int block = ((per + 63) / 64) * 64;
-    const size_t shm = sizeof(float) * (size_t)(3 * n_det + 2);
+    const size_t shm = sizeof(IN) * (size_t)(3 * n_det + 2);
     if (shm > 64 * 1024) return SKEI_ERANGE;
     const dim3 grid(rows);
-#define SKEI_RAMP_CASE(P)                                                                              \
-    case P:                                                                                            \
-        hipLaunchKernelGGL((k_ramp<P>), grid, dim3(block), shm, st, p, n_det, g->hodd, scale, q); \
+#define SKEI_RAMP_CASE(P)                                                                                  \
+    case P:                                                                                                \
+        hipLaunchKernelGGL((k_ramp<P, IN>), grid, dim3(block), shm, st, p, n_det, g->hodd, scale, q); \
         break;
     switch (rpt) {
         SKEI_RAMP_CASE(1)
@@ -80,6 +80,14 @@ int launch_ramp(const skei_geom *g, const float *p, int rows, float scale, float
     }
 #undef SKEI_RAMP_CASE
     return check_launch();
+}
+
+}  // namespace
+
+int launch_ramp(const skei_geom *g, const float *pf, const double *pd, int rows, float scale, float *q,
+                hipStream_t st)
+{
+    return pd ? ramp_launch<double>(g, pd, rows, scale, q, st) : ramp_launch<float>(g, pf, rows, scale, q, st);
 }
 
 }  // namespace skei

@@ -22,17 +22,20 @@ struct Sample {
 };
 
 // The one place where a sample point and its bilinear fractions are computed.
-__device__ __forceinline__ Sample sample_point(int i, int j, float c, float s, float cN)
+// Positions are formed in double precision (a float position near the image
+// border would carry ~ulp(N) of rounding into every weight).
+__device__ __forceinline__ Sample sample_point(int i, int j, float c, float s, double cN)
 {
-    const float X = (float)j - cN, Y = (float)i - cN;
-    const float u = fmaf(c, X, fmaf(s, Y, cN));
-    const float v = fmaf(-s, X, fmaf(c, Y, cN));
-    const float fu = floorf(u), fv = floorf(v);
+    const double X = (double)j - cN, Y = (double)i - cN;
+    const double cd = c, sd = s;
+    const double u = fma(cd, X, fma(sd, Y, cN));
+    const double v = fma(-sd, X, fma(cd, Y, cN));
+    const double fu = floor(u), fv = floor(v);
     Sample r;
     r.j0 = (int)fu;
     r.i0 = (int)fv;
-    r.au = u - fu;
-    r.av = v - fv;
+    r.au = (float)(u - fu);
+    r.av = (float)(v - fv);
     return r;
 }
 
@@ -44,7 +47,7 @@ __global__ void __launch_bounds__(256) k_rotate(const float *__restrict__ x, int
     if (p >= n * n) return;
     const int b = bc / copies, c = bc - b * copies;
     const int i = p / n, j = p - i * n;
-    const float cN = 0.5f * (float)(n - 1);
+    const double cN = 0.5 * (double)(n - 1);
     const Sample sp = sample_point(i, j, cs[2 * c], cs[2 * c + 1], cN);
     const float *img = x + (size_t)b * n * n;
     float acc = 0.0f;
@@ -63,46 +66,59 @@ __global__ void __launch_bounds__(256) k_rotate(const float *__restrict__ x, int
 }
 
 // g[b][p'] = alpha * sum_c sum_p T_c[p][p'] h[b][c][p] + beta * add[b][p']
+// A workgroup covers 64 consecutive pixels x 4 copy groups (copies c = grp,
+// grp+4, ...); the four partial sums are added in a fixed order through LDS.
+constexpr int kRotPix = 64, kRotGroups = 4;
+
 __global__ void __launch_bounds__(256) k_rotate_adj(const float *__restrict__ h, int n, int copies,
                                                     const float *__restrict__ cs, float alpha,
                                                     const float *__restrict__ add, float beta,
                                                     float *__restrict__ g)
 {
-    const int p = blockIdx.x * 256 + threadIdx.x;
+    __shared__ float part[kRotGroups][kRotPix];
+    const int px = threadIdx.x & (kRotPix - 1), grp = threadIdx.x / kRotPix;
+    const int p = blockIdx.x * kRotPix + px;
     const int b = blockIdx.y;
-    if (p >= n * n) return;
-    const int ip = p / n, jp = p - ip * n;
-    const float cN = 0.5f * (float)(n - 1);
-    const float Xp = (float)jp - cN, Yp = (float)ip - cN;
+    const bool in = p < n * n;
     float acc = 0.0f;
-    for (int c = 0; c < copies; c++) {
-        const float co = cs[2 * c], si = cs[2 * c + 1];
-        const float* hc = h + ((size_t)b * copies + c) * n * n;
-        // centre of the candidate set: the output position whose sample is p'
-        const float colc = fmaf(co, Xp, fmaf(-si, Yp, cN));
-        const float rowc = fmaf(si, Xp, fmaf(co, Yp, cN));
-        const float hw = fabsf(co) + fabsf(si) + 1e-3f;
-        const int jlo = (int)ceilf(colc - hw), ilo = (int)ceilf(rowc - hw);
+    if (in) {
+        const int ip = p / n, jp = p - ip * n;
+        const double cN = 0.5 * (double)(n - 1);
+        const double Xp = (double)jp - cN, Yp = (double)ip - cN;
+        for (int c = grp; c < copies; c += kRotGroups) {
+            const float co = cs[2 * c], si = cs[2 * c + 1];
+            const float *hc = h + ((size_t)b * copies + c) * n * n;
+            // centre of the candidate set: the output position whose sample is p'
+            const double colc = fma((double)co, Xp, fma(-(double)si, Yp, cN));
+            const double rowc = fma((double)si, Xp, fma((double)co, Yp, cN));
+            const double hw = fabs((double)co) + fabs((double)si) + 1e-6;
+            const int jlo = (int)ceil(colc - hw), ilo = (int)ceil(rowc - hw);
 #pragma unroll
-        for (int di = 0; di < 3; di++) {
-            const int i = ilo + di;
-            if (i < 0 || i >= n) continue;
+            for (int di = 0; di < 3; di++) {
+                const int i = ilo + di;
+                if (i < 0 || i >= n) continue;
 #pragma unroll
-            for (int dj = 0; dj < 3; dj++) {
-                const int j = jlo + dj;
-                if (j < 0 || j >= n) continue;
-                const Sample sp = sample_point(i, j, co, si, cN);
-                const int ei = ip - sp.i0, ej = jp - sp.j0;
-                if ((unsigned)ei > 1u || (unsigned)ej > 1u) continue;
-                const float wv = ei ? sp.av : 1.0f - sp.av;
-                const float wu = ej ? sp.au : 1.0f - sp.au;
-                acc = fmaf(wv * wu, hc[(size_t)i * n + j], acc);
+                for (int dj = 0; dj < 3; dj++) {
+                    const int j = jlo + dj;
+                    if (j < 0 || j >= n) continue;
+                    const Sample sp = sample_point(i, j, co, si, cN);
+                    const int ei = ip - sp.i0, ej = jp - sp.j0;
+                    if ((unsigned)ei > 1u || (unsigned)ej > 1u) continue;
+                    const float wv = ei ? sp.av : 1.0f - sp.av;
+                    const float wu = ej ? sp.au : 1.0f - sp.au;
+                    acc = fmaf(wv * wu, hc[(size_t)i * n + j], acc);
+                }
             }
         }
     }
-    float v = alpha * acc;
-    if (add) v = fmaf(beta, add[(size_t)b * n * n + p], v);
-    g[(size_t)b * n * n + p] = v;
+    part[grp][px] = acc;
+    __syncthreads();
+    if (grp == 0 && in) {
+        const float s = ((part[0][px] + part[1][px]) + part[2][px]) + part[3][px];
+        float v = alpha * s;
+        if (add) v = fmaf(beta, add[(size_t)b * n * n + p], v);
+        g[(size_t)b * n * n + p] = v;
+    }
 }
 
 }  // namespace
@@ -117,7 +133,7 @@ int launch_rotate(const float *x, int batch, int copies, int n, const float *cs,
 int launch_rotate_adj(const float *h, int batch, int copies, int n, const float *cs, float alpha,
                       const float *add, float beta, float *g, hipStream_t st)
 {
-    const dim3 grid((n * n + 255) / 256, batch);
+    const dim3 grid((n * n + kRotPix - 1) / kRotPix, batch);
     hipLaunchKernelGGL(k_rotate_adj, grid, dim3(256), 0, st, h, n, copies, cs, alpha, add, beta, g);
     return check_launch();
 }

@@ -19,15 +19,17 @@ namespace skei {
 //     u(k, M) = base + k * inv_m + M * du ,
 // i.e. u = (s_k - (M - cN) c_M) / c_m + cN.
 struct AngleRow {
-    float c, s;      // cos theta, sin theta
-    float inv_m;     // 1 / c_m
-    float du;        // -c_M / c_m
-    float base;      // -cD / c_m + cN (1 + c_M / c_m)
-    float scale;     // 1 / |c_m|   (Joseph step length)
-    float w;         // |c_m| = max(|cos|, |sin|)
-    float inv_w2;    // 1 / w^2
-    int rows;        // 1: major axis = image rows
-    int pad_[7];
+    int64_t base_fx;  // base, inv_m and du in 32.32 fixed point (exact ray stepping)
+    int64_t inv_fx;
+    int64_t du_fx;
+    double scale;     // 1 / |c_m|   (Joseph step length), double
+    float c, s;       // cos theta, sin theta
+    float w;          // |c_m| = max(|cos|, |sin|)
+    float inv_w2;     // 1 / w^2
+    float du;         // -c_M / c_m               (float copies for range estimates)
+    float base;       // -cD / c_m + cN (1 + c_M / c_m)
+    float inv_m;      // 1 / c_m
+    int rows;         // 1: major axis = image rows
 };
 static_assert(sizeof(AngleRow) == 64, "AngleRow layout");
 
@@ -35,9 +37,7 @@ static_assert(sizeof(AngleRow) == 64, "AngleRow layout");
 // carries PAD zeros on each side so that clamped tap positions read zeros.
 constexpr int kLinePad = 4;
 
-// Pixel tile of the pixel-driven gathers and the detector window they stage.
-constexpr int kTile = 16;
-constexpr int kWin = 32;
+// Angles staged per LDS pass by the pixel-driven gathers.
 constexpr int kAngleChunk = 64;
 
 // Residual / reduction modes shared by kernels.
@@ -52,16 +52,25 @@ int check_launch();   // maps hipGetLastError to SKEI_OK / SKEI_ELAUNCH
 // All take device pointers and enqueue on `st`.  Shapes are validated by the
 // C ABI layer before these are called.
 
+// Launch shape of the ray-driven kernels (0 = automatic choice):
+//   group: listed angles per workgroup (they share every staged image chunk)
+//   lines: image lines per LDS chunk
+//   split: detector segments per angle
+struct RayTune {
+    int group = 0, lines = 0, split = 0;
+};
+
 // Ray-driven Joseph projection (and its MC-residual form):
 //   plain:   y[b][r][k] = (A_S x[b])[r][k]
-//   resid:   y[b][r][k] = yfull[b][idx[r]][k] - (A_S x[b])[r][k]; partial[] = per-block sum of y^2
-int launch_radon_fwd(const skei_geom *g, const float *x, int batch, const int32_t *idx, int m,
-                     float *y, const float *yfull, double *partial, int lines_per_chunk, hipStream_t st);
-size_t radon_fwd_partials(const skei_geom *g, int batch, int m);
+//   resid:   y[b][r][k] = yfull[b][idx[r]][k] - (A_S x[b])[r][k]  (difference taken in double);
+//            partial[] = per-workgroup sums of y^2
+int launch_radon_fwd(const skei_geom *g, const float *x, int batch, const int32_t *idx, int m, float *y,
+                     const float *yfull, double *partial, const RayTune &tune, hipStream_t st);
+size_t radon_fwd_partials(const skei_geom *g, int batch, int m, const RayTune &tune);
 
-// Ray-driven B_S^T (unscaled).
-int launch_bp_T(const skei_geom *g, const float *x, int batch, const int32_t *idx, int m,
-                float *q, int lines_per_chunk, hipStream_t st);
+// Ray-driven B_S^T (unscaled), written as float (qf) or double (qd; exactly one non-null).
+int launch_bp_T(const skei_geom *g, const float *x, int batch, const int32_t *idx, int m, float *qf,
+                double *qd, const RayTune &tune, hipStream_t st);
 
 // Pixel-driven gathers over the listed angles.
 //   joseph: A_S^T y   ;  bp: scale * B_S q
@@ -72,8 +81,10 @@ int launch_backproject(const skei_geom *g, const float *q, int batch, const int3
                        float scale, float *x, const float *other, double *partial, hipStream_t st);
 size_t gather_partials(const skei_geom *g, int batch);
 
-// Ram-Lak ramp along rows, double accumulation, times `scale`.
-int launch_ramp(const skei_geom *g, const float *p, int rows, float scale, float *q, hipStream_t st);
+// Ram-Lak ramp along rows, double accumulation, times `scale`; the input is
+// float (pf) or double (pd; exactly one non-null).
+int launch_ramp(const skei_geom *g, const float *pf, const double *pd, int rows, float scale, float *q,
+                hipStream_t st);
 
 // Rotation and its transpose (copies summed).  rotate_adj optionally fuses
 // g = alpha * sum_c T_c^T h[b][c] + beta * add[b].

@@ -62,7 +62,7 @@ def test_fused_ei_loss_grad_matches_oracle(skei, orc, shape):
     k = kappa(orc, x0, y, na, idx, cs, lam, want_g)
     print(f"loss {got_l:.9e} vs {want_l:.9e} rel {e_l:.2e}; grad relerr {e_g:.2e}; kappa {k:.1f}")
     assert e_l < 1e-5
-    assert e_g < 1e-5 * max(1.0, k)
+    assert e_g < 1e-5
     # deterministic: a second call gives bitwise the same loss and gradient
     loss2, grad2 = step(to_dev(x0))
     assert float(loss2.item()) == got_l and torch.equal(grad2, grad)
@@ -84,4 +84,4 @@ def test_autograd_matches_fused_step(skei, orc):
     print(f"\nautograd loss {loss.item():.9e} fused {l2.item():.9e} oracle {want_l:.9e}")
     assert abs(loss.item() - want_l) < 1e-5 * want_l
     assert relerr(host(x.grad), host(g2)) < 1e-5
-    assert relerr(host(x.grad), want_g) < 1e-4
+    assert relerr(host(x.grad), want_g) < 1e-5
