@@ -83,6 +83,14 @@ int skei_geom_create(int n, int n_angles, int n_det, skei_geom **out);
 int skei_geom_destroy(skei_geom *g);
 int skei_geom_info(const skei_geom *g, int *n, int *n_angles, int *n_det);
 
+/* Launch shape of the ray-driven kernels (forward projector, B_S^T) used by
+ * later calls on this geometry: `group` listed angles per workgroup (1..8),
+ * `lines` image lines per LDS chunk, `split` detector segments per angle;
+ * 0 keeps the built-in choice.  Results do not depend on these (bitwise);
+ * only speed does.  Not to be changed while calls on the geometry run. */
+enum { SKEI_OP_FWD = 0, SKEI_OP_BPT = 1 };
+int skei_geom_set_tuning(skei_geom *g, int op, int group, int lines, int split);
+
 /* y = A_S x   (Sec. 3.1 sketched forward operator; Joseph's method).
  * x [batch][N][N] -> y [batch][m][N_det].  Row r is the Joseph line sum
  * of every image along the rays of angle angle_idx[r]: step over the

@@ -30,6 +30,7 @@ _SIGS = {
     "skei_strerror": (c_char_p, [c_int]),
     "skei_geom_create": (c_int, [c_int, c_int, c_int, ctypes.POINTER(c_void_p)]),
     "skei_geom_destroy": (c_int, [c_void_p]),
+    "skei_geom_set_tuning": (c_int, [c_void_p, c_int, c_int, c_int, c_int]),
     "skei_geom_info": (c_int, [c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
     "skei_radon_fwd": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_int, c_void_p, c_void_p]),
     "skei_radon_adj": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_int, c_void_p, c_void_p]),

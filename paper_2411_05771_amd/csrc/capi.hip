@@ -55,9 +55,10 @@ EiSizes ei_sizes(const skei_geom *g, int batch, int m_mc, int m, int copies)
     s.img = bc * nn;
     s.sino = bc * (size_t)m * g->n_det;
     s.mc = (size_t)batch * m_mc * g->n_det;
-    s.part_mc = radon_fwd_partials(g, batch, m_mc, RayTune{});
+    s.part_mc = radon_fwd_partials(g, batch, m_mc, g->tune_fwd);
     s.part_ei = gather_partials(g, (int)bc);
-    s.total = align256(s.img * 4) * 2            // z (later d), r
+    s.total = align256(s.img * 4) * 4            // z (later d), zT, r, rT
+              + align256(nn * batch * 4)         // xT
               + align256(s.sino * 8)             // ys (A_S z as float, later B_S^T r as double)
               + align256(s.sino * 4)             // qs (H ys, later (pi/m) H B_S^T r)
               + align256(s.mc * 4)               // r_MC
@@ -103,7 +104,7 @@ int skei_radon_fwd(const skei_geom *g, const float *x, int batch, const int32_t 
 {
     int rc = check_geom_op(g, x, batch, angle_idx, m, y);
     if (rc) return rc;
-    return launch_radon_fwd(g, x, batch, angle_idx, m, y, nullptr, nullptr, RayTune{}, S(stream));
+    return launch_radon_fwd(g, x, nullptr, batch, angle_idx, m, y, nullptr, nullptr, g->tune_fwd, S(stream));
 }
 
 int skei_radon_adj(const skei_geom *g, const float *y, int batch, const int32_t *angle_idx, int m, float *x,
@@ -133,15 +134,17 @@ int skei_backproject_T(const skei_geom *g, const float *x, int batch, const int3
 {
     int rc = check_geom_op(g, x, batch, angle_idx, m, q);
     if (rc) return rc;
-    return launch_bp_T(g, x, batch, angle_idx, m, q, nullptr, RayTune{}, S(stream));
+    return launch_bp_T(g, x, nullptr, batch, angle_idx, m, q, nullptr, g->tune_bpt, S(stream));
 }
 
 size_t skei_fbp_workspace_bytes(const skei_geom *g, int batch, int m)
 {
     if (!g || batch <= 0 || m <= 0) return 0;
     // fbp keeps the filtered sinogram (float); fbp_adj keeps B_S^T x in double
-    // so that the high-pass ramp does not amplify its rounding
-    return align256((size_t)batch * m * g->n_det * sizeof(double));
+    // (so that the high-pass ramp does not amplify its rounding) and the
+    // transposed images (contiguous staging for column-stepping angles)
+    return align256((size_t)batch * m * g->n_det * sizeof(double)) +
+           align256((size_t)batch * g->n * g->n * sizeof(float));
 }
 
 int skei_fbp(const skei_geom *g, const float *y, int batch, const int32_t *angle_idx, int m, float *x, void *work,
@@ -165,7 +168,11 @@ int skei_fbp_adj(const skei_geom *g, const float *x, int batch, const int32_t *a
     if (!work) return SKEI_EINVAL;
     if (work_bytes < skei_fbp_workspace_bytes(g, batch, m)) return SKEI_ESPACE;
     double *t = static_cast<double *>(work);
-    rc = launch_bp_T(g, x, batch, angle_idx, m, nullptr, t, RayTune{}, S(stream));
+    float *xT = reinterpret_cast<float *>(static_cast<char *>(work) +
+                                          align256((size_t)batch * m * g->n_det * sizeof(double)));
+    rc = launch_transpose(x, batch, g->n, xT, S(stream));
+    if (rc) return rc;
+    rc = launch_bp_T(g, x, xT, batch, angle_idx, m, nullptr, t, g->tune_bpt, S(stream));
     if (rc) return rc;
     return launch_ramp(g, nullptr, t, batch * m, (float)(kPi / m), y, S(stream));
 }
@@ -214,7 +221,10 @@ int skei_ei_loss_grad(const skei_geom *g, const float *x, const float *y, int ba
     if (work_bytes < sz.total) return SKEI_ESPACE;
     Carver cv{static_cast<char *>(work), work_bytes};
     float *z = cv.take<float>(sz.img);
+    float *zT = cv.take<float>(sz.img);
     float *r = cv.take<float>(sz.img);
+    float *rT = cv.take<float>(sz.img);
+    float *xT = cv.take<float>((size_t)g->n * g->n * batch);
     double *ysd = cv.take<double>(sz.sino);
     float *ys = reinterpret_cast<float *>(ysd);
     float *qs = cv.take<float>(sz.sino);
@@ -229,17 +239,21 @@ int skei_ei_loss_grad(const skei_geom *g, const float *x, const float *y, int ba
     const float pim = (float)(kPi / m);
     int rc;
     // forward: z = T x ; ys = A_S z ; qs = H ys ; r = z - (pi/m) B_S qs ; r_MC = y[mc] - A_mc x
-    if ((rc = staged(SKEI_STAGE_ROTATE, st, [&] { return launch_rotate(x, batch, copies, g->n, cos_sin, z, st); })))
+    if ((rc = staged(SKEI_STAGE_ROTATE, st, [&] { return launch_rotate(x, batch, copies, g->n, cos_sin, z, st, zT); })))
         return rc;
     if ((rc = staged(SKEI_STAGE_FWD_SKETCH, st,
-                     [&] { return launch_radon_fwd(g, z, bc, angle_idx, m, ys, nullptr, nullptr, RayTune{}, st); })))
+                     [&] { return launch_radon_fwd(g, z, zT, bc, angle_idx, m, ys, nullptr, nullptr, g->tune_fwd, st); })))
         return rc;
     if ((rc = staged(SKEI_STAGE_RAMP, st, [&] { return launch_ramp(g, ys, nullptr, bc * m, 1.0f, qs, st); }))) return rc;
     if ((rc = staged(SKEI_STAGE_BP_RESID, st,
-                     [&] { return launch_backproject(g, qs, bc, angle_idx, m, pim, r, z, pei, st); })))
+                     [&] { return launch_backproject(g, qs, bc, angle_idx, m, pim, r, z, pei, st, rT); })))
         return rc;
     if ((rc = staged(SKEI_STAGE_FWD_MC, st,
-                     [&] { return launch_radon_fwd(g, x, batch, mc_idx, m_mc, rmc, y, pmc, RayTune{}, st); })))
+                     [&] {
+                         int rc2 = launch_transpose(x, batch, g->n, xT, st);
+                         if (rc2) return rc2;
+                         return launch_radon_fwd(g, x, xT, batch, mc_idx, m_mc, rmc, y, pmc, g->tune_fwd, st);
+                     })))
         return rc;
     if ((rc = staged(SKEI_STAGE_REDUCE, st, [&] {
              return launch_reduce2(pmc, sz.part_mc, 1.0, pei, sz.part_ei, (double)lambda / copies, loss, st);
@@ -248,7 +262,7 @@ int skei_ei_loss_grad(const skei_geom *g, const float *x, const float *y, int ba
     if (!grad) return SKEI_OK;
     // backward: ys = B_S^T r ; qs = (pi/m) H ys ; z = r - A_S^T qs ;
     //           amc = A_mc^T r_MC ; grad = (2 lambda / C) sum_c T_c^T z - 2 amc
-    if ((rc = staged(SKEI_STAGE_BP_T, st, [&] { return launch_bp_T(g, r, bc, angle_idx, m, nullptr, ysd, RayTune{}, st); })))
+    if ((rc = staged(SKEI_STAGE_BP_T, st, [&] { return launch_bp_T(g, r, rT, bc, angle_idx, m, nullptr, ysd, g->tune_bpt, st); })))
         return rc;
     if ((rc = staged(SKEI_STAGE_RAMP_T, st, [&] { return launch_ramp(g, nullptr, ysd, bc * m, pim, qs, st); }))) return rc;
     if ((rc = staged(SKEI_STAGE_ADJ_SKETCH, st,

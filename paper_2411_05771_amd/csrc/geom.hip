@@ -124,6 +124,22 @@ int skei_geom_destroy(skei_geom *g)
     return SKEI_OK;
 }
 
+int skei_geom_set_tuning(skei_geom *g, int op, int group, int lines, int split)
+{
+    if (!g || group < 0 || group > 8 || lines < 0 || lines > 64 || split < 0 || split > 64) return SKEI_EINVAL;
+    skei::RayTune t;
+    t.group = group;
+    t.lines = lines;
+    t.split = split;
+    if (op == SKEI_OP_FWD)
+        g->tune_fwd = t;
+    else if (op == SKEI_OP_BPT)
+        g->tune_bpt = t;
+    else
+        return SKEI_EINVAL;
+    return SKEI_OK;
+}
+
 int skei_geom_info(const skei_geom *g, int *n, int *n_angles, int *n_det)
 {
     if (!g) return SKEI_EINVAL;

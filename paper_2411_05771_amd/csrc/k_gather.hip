@@ -51,7 +51,8 @@ __global__ void __launch_bounds__(256 * GA) k_gather(const float *__restrict__ i
                                                      const int32_t *__restrict__ idx, int m,
                                                      const AngleRow *__restrict__ tab, float scale,
                                                      float *__restrict__ out, const float *__restrict__ other,
-                                                     double *__restrict__ partial, int total)
+                                                     double *__restrict__ partial, int total,
+                                                     float *__restrict__ outT)
 {
     constexpr int TILE = 16, NPIX = TILE * TILE, BS = NPIX * GA, WIN = 2 * TILE;
     __shared__ GatherAngle prm[kAngleChunk];
@@ -59,6 +60,7 @@ __global__ void __launch_bounds__(256 * GA) k_gather(const float *__restrict__ i
     __shared__ float iw2[kAngleChunk];                // 1/w^2 (Joseph weights)
     __shared__ float2 win[kAngleChunk * WIN];
     __shared__ float part[GA][NPIX];
+    __shared__ float tileT[TILE][TILE + 1];
     __shared__ double red[NPIX / 64];
 
     int item;
@@ -134,14 +136,21 @@ __global__ void __launch_bounds__(256 * GA) k_gather(const float *__restrict__ i
     // the threads of angle group 0 write the tile
     const int i = i0 + dy, j = j0 + dx;
     double ss = 0.0;
+    float v = 0.0f;
     if (ga == 0 && i < n && j < n) {
         const size_t o = ((size_t)b * n + i) * n + j;
-        float v = acc * scale;
+        v = acc * scale;
         if (MODE == kResidSub) {
             v = other[o] - v;
             ss = (double)v * (double)v;
         }
         out[o] = v;
+    }
+    if (outT) {   // the tile again, transposed through LDS (coalesced stores)
+        if (ga == 0) tileT[dy][dx] = v;
+        __syncthreads();
+        const int it = j0 + dy, jt = i0 + dx;
+        if (ga == 0 && it < n && jt < n) outT[((size_t)b * n + it) * n + jt] = tileT[dx][dy];
     }
     if (MODE == kResidSub && partial) {
         ss = wave_sum(ss);
@@ -160,7 +169,7 @@ int angle_groups(int m) { return m >= 256 ? 4 : m >= 64 ? 2 : 1; }
 
 template <int KIND, int GA>
 int gather_launch_g(const skei_geom *g, const float *in, int batch, const int32_t *idx, int m, float scale,
-                    float *out, const float *other, double *partial, hipStream_t st)
+                    float *out, const float *other, double *partial, hipStream_t st, float *outT)
 {
     const int n = g->n;
     const long long tiles = (long long)((n + 15) / 16) * ((n + 15) / 16);
@@ -169,21 +178,21 @@ int gather_launch_g(const skei_geom *g, const float *in, int batch, const int32_
     const dim3 grid((unsigned)(8 * ((total + 7) / 8))), block(256 * GA);
     if (other)
         hipLaunchKernelGGL((k_gather<KIND, kResidSub, GA>), grid, block, 0, st, in, n, g->n_det, idx, m, g->tab,
-                           scale, out, other, partial, (int)total);
+                           scale, out, other, partial, (int)total, outT);
     else
         hipLaunchKernelGGL((k_gather<KIND, kPlain, GA>), grid, block, 0, st, in, n, g->n_det, idx, m, g->tab,
-                           scale, out, nullptr, nullptr, (int)total);
+                           scale, out, nullptr, nullptr, (int)total, outT);
     return check_launch();
 }
 
 template <int KIND>
 int gather_launch(const skei_geom *g, const float *in, int batch, const int32_t *idx, int m, float scale,
-                  float *out, const float *other, double *partial, hipStream_t st)
+                  float *out, const float *other, double *partial, hipStream_t st, float *outT = nullptr)
 {
     switch (angle_groups(m)) {
-    case 4: return gather_launch_g<KIND, 4>(g, in, batch, idx, m, scale, out, other, partial, st);
-    case 2: return gather_launch_g<KIND, 2>(g, in, batch, idx, m, scale, out, other, partial, st);
-    default: return gather_launch_g<KIND, 1>(g, in, batch, idx, m, scale, out, other, partial, st);
+    case 4: return gather_launch_g<KIND, 4>(g, in, batch, idx, m, scale, out, other, partial, st, outT);
+    case 2: return gather_launch_g<KIND, 2>(g, in, batch, idx, m, scale, out, other, partial, st, outT);
+    default: return gather_launch_g<KIND, 1>(g, in, batch, idx, m, scale, out, other, partial, st, outT);
     }
 }
 
@@ -206,9 +215,9 @@ int launch_radon_adj(const skei_geom *g, const float *y, int batch, const int32_
 }
 
 int launch_backproject(const skei_geom *g, const float *q, int batch, const int32_t *idx, int m, float scale,
-                       float *x, const float *other, double *partial, hipStream_t st)
+                       float *x, const float *other, double *partial, hipStream_t st, float *xT)
 {
-    return gather_launch<kBackproject>(g, q, batch, idx, m, scale, x, other, partial, st);
+    return gather_launch<kBackproject>(g, q, batch, idx, m, scale, x, other, partial, st, xT);
 }
 
 }  // namespace skei

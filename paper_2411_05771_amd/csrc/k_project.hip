@@ -5,17 +5,24 @@
 // detector segment; its rays are (angle, detector) pairs, i.e. families of
 // parallel lines that cross every image line along the angle's major axis.
 // The image is streamed through LDS in chunks of R lines -- rows for angles
-// that Joseph steps along rows, columns (transposed on the way in) for the
-// others, in two passes when a group straddles 45 or 135 degrees -- so every
-// tap is an LDS read and the G angles share each staged chunk.  Only the span
-// of each line that the group's rays can touch is staged.
+// that Joseph steps along rows, columns for the others (two passes when a
+// group straddles 45 or 135 degrees) -- so every tap is an LDS read and the G
+// angles share each staged chunk.
+//
+// Staging uses the LDS DMA path (global_load_lds): each wave instruction
+// moves a contiguous run of a line straight from global memory into LDS, no
+// registers involved -- 16-byte lanes along image rows, 4-byte lanes gathering
+// a column (which lands transposed, i.e. line-contiguous, in LDS).  Two LDS
+// buffers alternate: the DMA of chunk c+1 is in flight while chunk c is
+// marched.  Only the span of each line that the group's rays can touch is
+// staged.
 //
 // Ray positions are 32.32 fixed-point numbers stepped by exact integer adds
 // (u(k, M+1) = u(k, M) + du), so the interpolation position carries no
 // rounding that grows with the image size; out-of-image taps are clamped onto
-// zero-padded LDS borders instead of being branched around.  Sums are kept in
-// float over aligned 16-line blocks (forward) or a line (B^T) and in double
-// across them, so results do not depend on the launch shape.
+// zero LDS borders instead of being branched around.  Sums are kept in float
+// over aligned 16-line blocks (forward) or a line (B^T) and in double across
+// them, so results do not depend on the launch shape.
 //
 // Workgroups are mapped XCD-major: consecutive work items (same image) go to
 // the same XCD, so each XCD's L2 holds only its share of the images.
@@ -26,28 +33,28 @@
 namespace skei {
 namespace {
 
-constexpr int kBlock = 256;                  // threads per workgroup
+typedef __attribute__((address_space(1))) const void gmem_t;
+typedef __attribute__((address_space(3))) void lmem_t;
+
+constexpr int kBlock = 256;                  // threads per workgroup (4 waves)
+constexpr int kWaves = kBlock / 64;
 constexpr int kMaxG = 8;                     // listed angles per workgroup
 constexpr int kRaysMax = 8 * kBlock;         // rays per workgroup (8 per thread)
+constexpr size_t kLdsBudget = 40 * 1024;     // both staging buffers
 constexpr float kTwoM32 = 2.3283064365386963e-10f;   // 2^-32
 
 enum Kind : int { kFwd = 0, kBpT = 1 };
 
 struct Plan {
-    int G, nseg, seg, rpt, R, stride, ngroups;
+    int G, nseg, seg, rpt, R, pitch, ngroups;
     long long total;
     size_t shm;
 };
 
-int line_stride(int n)
-{
-    const int s = n + 2 * kLinePad;
-    return (s % 2 == 0) ? s + 1 : s;         // odd stride: transposed staging spreads over banks
-}
+// LDS line pitch in floats: kLinePad zero entries on each side, 16-byte multiple.
+int line_pitch(int n) { return ((n + 2 * kLinePad) + 3) & ~3; }
 
-// Launch plan.  elem = bytes per staged LDS entry (8: value/difference pairs,
-// 4: plain values); `units_per_line` bounds the staged entries of a line.
-int make_plan(const skei_geom *g, int batch, int m, const RayTune &t, size_t elem, Plan &p)
+int make_plan(const skei_geom *g, int batch, int m, const RayTune &t, Plan &p)
 {
     const int n = g->n, nd = g->n_det;
     const long long base_items = (long long)batch * m;
@@ -67,14 +74,12 @@ int make_plan(const skei_geom *g, int batch, int m, const RayTune &t, size_t ele
     p.nseg = nseg;
     p.seg = (nd + nseg - 1) / nseg;
     p.rpt = (G * p.seg + kBlock - 1) / kBlock;
-    p.stride = line_stride(n);
-    const int r_lds = (int)((size_t)(34 * 1024) / ((size_t)p.stride * elem));
+    p.pitch = line_pitch(n);
+    const int r_lds = (int)(kLdsBudget / (2 * (size_t)p.pitch * sizeof(float)));
     int R = std::min(std::max(r_lds, 1), std::min(64, n));
     if (t.lines > 0) R = std::min(R, t.lines);
-    if (R < 1) return SKEI_ERANGE;
-    if (R >= 8) R &= ~3;                      // keep chunk starts 16-byte aligned when possible
     p.R = R;
-    p.shm = (size_t)R * p.stride * elem;
+    p.shm = 2 * (size_t)R * p.pitch * sizeof(float);
     if (p.shm > 64 * 1024) return SKEI_ERANGE;
     p.ngroups = (m + G - 1) / G;
     p.total = (long long)batch * p.ngroups * p.nseg;
@@ -124,76 +129,11 @@ __device__ __forceinline__ void ray_range(float u0, float du, int n, int &lo, in
     hi = (int)fminf(ceilf(fmaxf(t1, t2)) + 1.0f, (float)(n - 1));
 }
 
-// Index walk over a flattened (outer, inner) space: each thread starts at
-// element `tid` and advances by kBlock elements with a carry (no division in
-// the loops).
-struct Walk {
-    int o, i;
-    __device__ Walk(int tid, int inner) : o(tid / inner), i(tid % inner) {}
-    __device__ __forceinline__ void step(int so, int si, int inner)
-    {
-        i += si;
-        o += so;
-        if (i >= inner) {
-            i -= inner;
-            o += 1;
-        }
-    }
-};
-
-// Staging of lines [M0, M0+Rc), minor positions [cl, cl+W).  Row mode: lanes
-// run along a row (coalesced loads, consecutive LDS entries).  Column mode:
-// lanes run across the chunk's columns (coalesced loads of each row segment;
-// the odd line stride spreads the transposed LDS writes over the banks).
-// PAIRS entries hold (v[j], (v[j+1] - v[j]) * 2^-32) for the fixed-point
-// fraction; plain entries hold v[j].  Latency is hidden by the other
-// workgroups resident on the CU, not by registers.
-template <bool PAIRS, typename T>
-__device__ __forceinline__ void stage(T *lds, int stride, const float *__restrict__ img, int n, bool rows, int M0,
-                                      int Rc, int cl, int W)
-{
-    const int tid = threadIdx.x;
-    const int total = Rc * W;
-    if (total <= 0) return;
-    const int inner = rows ? W : Rc;
-    Walk w(tid, inner);
-    const int so = kBlock / inner, si = kBlock % inner;
-    for (int e = tid; e < total; e += kBlock, w.step(so, si, inner)) {
-        const int line = rows ? w.o : w.i;
-        const int pos = cl + (rows ? w.i : w.o);
-        const float *p0;
-        size_t next;
-        if (rows) {
-            p0 = img + (size_t)(M0 + line) * n + pos;
-            next = 1;
-        } else {
-            p0 = img + (size_t)pos * n + M0 + line;
-            next = (size_t)n;
-        }
-        const float v = (pos >= 0 && pos < n) ? p0[0] : 0.0f;
-        T *d = lds + line * stride + kLinePad + pos;
-        if constexpr (PAIRS) {
-            const float nx = (pos + 1 < n) ? p0[next] : 0.0f;
-            *d = make_float2(v, (nx - v) * kTwoM32);
-        } else {
-            *d = v;
-        }
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ void zero_borders(T *lds, int n, int stride, int R)
-{
-    const int nb = stride - n;   // border entries per line: [0, PAD) and [PAD+n, stride)
-    for (int e = threadIdx.x; e < R * nb; e += kBlock) {
-        const int l = e / nb, p = e - l * nb;
-        lds[l * stride + (p < kLinePad ? p : n + p)] = T{};
-    }
-}
-
-// Minor-axis span touched by the group's rays of one pass over lines [M0, M0+Rc).
+// Minor-axis span [cl, cl+W) within [0, n) touched by the group's rays of one
+// pass over lines [M0, M0+Rc); widened by 3 entries each side, and aligned
+// to 4 entries for 16-byte DMA lanes.
 __device__ __forceinline__ void chunk_span(const AngleRow *ang, int gcount, int pass, int k0, int k1, int M0, int Rc,
-                                           int n, int lo_clip, int &cl, int &W)
+                                           int n, int &cl, int &W)
 {
     float umin = 3.0e38f, umax = -3.0e38f;
     const float fk0 = (float)k0, fk1 = (float)k1, fm0 = (float)M0, fm1 = (float)(M0 + Rc - 1);
@@ -206,16 +146,56 @@ __device__ __forceinline__ void chunk_span(const AngleRow *ang, int gcount, int 
         umin = fminf(umin, fminf(fminf(c00, c01), fminf(c10, c11)));
         umax = fmaxf(umax, fmaxf(fmaxf(c00, c01), fmaxf(c10, c11)));
     }
-    const float lo = fmaxf(floorf(umin) - 3.0f, (float)lo_clip);
+    const float lo = fmaxf(floorf(umin) - 3.0f, 0.0f);
     const float hi = fminf(floorf(umax) + 4.0f, (float)(n - 1));
     if (!(hi >= lo)) {
         cl = 0;
         W = 0;
         return;
     }
-    cl = (int)lo;
+    cl = ((int)lo) & ~3;
     W = (int)hi - cl + 1;
 }
+
+// DMA of lines [M0, M0+Rc), positions [cl, cl+W), into LDS buffer `buf`
+// (entry p of line l at buf[l*pitch + kLinePad + p]).  Rows: each lane moves
+// 16 bytes (4 consecutive entries; n % 4 == 0 and cl % 4 == 0), 256 entries
+// per wave instruction.  Columns: each lane gathers one entry of the column,
+// 64 consecutive rows per wave instruction.  Lanes past the span are masked.
+__device__ __forceinline__ void stage_dma(float *buf, int pitch, const float *__restrict__ img, int n, bool rows,
+                                          int M0, int Rc, int cl, int W)
+{
+    if (W <= 0) return;
+    const int lane = threadIdx.x & 63;
+    // wave-uniform segment bookkeeping lives in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int end = cl + W;
+    if (rows && (n & 3) == 0) {
+        const int S = (W + 255) >> 8;
+        const int off = 4 * lane;
+        for (int sgi = wave; sgi < Rc * S; sgi += kWaves) {
+            const int l = sgi / S, s = sgi - l * S;
+            const int p0 = cl + (s << 8);
+            const float *src = img + (size_t)(M0 + l) * n + p0;      // uniform
+            if (p0 + off < end)
+                __builtin_amdgcn_global_load_lds((gmem_t *)(src + off), (lmem_t *)(buf + l * pitch + kLinePad + p0),
+                                                 16, 0, 0);
+        }
+    } else {
+        const int S = (W + 63) >> 6;
+        const size_t lane_step = rows ? (size_t)lane : (size_t)lane * n;
+        for (int sgi = wave; sgi < Rc * S; sgi += kWaves) {
+            const int l = sgi / S, s = sgi - l * S;
+            const int p0 = cl + (s << 6);
+            const float *src = rows ? img + (size_t)(M0 + l) * n + p0 : img + (size_t)p0 * n + (M0 + l);   // uniform
+            if (p0 + lane < end)
+                __builtin_amdgcn_global_load_lds((gmem_t *)(src + lane_step), (lmem_t *)(buf + l * pitch + kLinePad + p0),
+                                                 4, 0, 0);
+        }
+    }
+}
+
+__device__ __forceinline__ void dma_wait() { __builtin_amdgcn_s_waitcnt(0); }
 
 // ---------------------------------------------------------------------------
 // KIND kFwd: y[b][r][k] = (1/w) sum_M lerp(line_M, u(k, M))       (Joseph A_S)
@@ -225,23 +205,21 @@ __device__ __forceinline__ void chunk_span(const AngleRow *ang, int gcount, int 
 //   entries within 1/w of u; the four candidates j0-1 .. j0+2 cover them.
 // ---------------------------------------------------------------------------
 template <int KIND, int RPT, int MODE, typename OUT>
-__global__ void __launch_bounds__(kBlock) k_ray(const float *__restrict__ x, int n, int n_det,
+__global__ void __launch_bounds__(kBlock) k_ray(const float *__restrict__ x, const float *__restrict__ xT, int n,
+                                                int n_det,
                                                 const int32_t *__restrict__ idx, int m,
                                                 const AngleRow *__restrict__ tab, int G, int nseg, int seg,
-                                                int ngroups, long long total, int R, int stride,
+                                                int ngroups, long long total, int R, int pitch,
                                                 OUT *__restrict__ y, const float *__restrict__ yfull, int n_angles,
                                                 double *__restrict__ partial)
 {
-    constexpr bool PAIRS = KIND == kFwd;
     // Lowest tap entry read: j0 for the forward walk, j0 - 1 for B^T; taps
     // below -kLinePad (and above n + 1) are clamped onto the zero borders.
-    constexpr int kBias = PAIRS ? kLinePad : kLinePad - 1;
-    using Entry = typename std::conditional<PAIRS, float2, float>::type;
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    Entry *lds = reinterpret_cast<Entry *>(lds_raw);
+    constexpr int kBias = KIND == kFwd ? kLinePad : kLinePad - 1;
+    extern __shared__ __align__(16) float lds[];
     __shared__ AngleRow ang[kMaxG];
-    __shared__ int wrange[2][kBlock / 64];
-    __shared__ double red[kBlock / 64];
+    __shared__ int wrange[2][kWaves];
+    __shared__ double red[kWaves];
 
     long long item;
     if (!decode_item(total, item)) return;
@@ -253,15 +231,22 @@ __global__ void __launch_bounds__(kBlock) k_ray(const float *__restrict__ x, int
     const int k_begin = sg * seg, k_len = min(seg, n_det - k_begin);
     const int tid = threadIdx.x;
     if (tid < gcount) ang[tid] = tab[idx[r0 + tid]];
-    zero_borders(lds, n, stride, R);
+    // zero both buffers once: the DMA only ever writes inside [0, n) of a line
+    for (int e = tid; e < 2 * R * pitch; e += kBlock) lds[e] = 0.0f;
     __syncthreads();
     const float *img = x + (size_t)b * n * n;
+    const int buf_stride = R * pitch;
 
+    // Ray slot of (thread, q): blocks of 16 consecutive detectors are dealt
+    // round-robin to the waves, so every wave spans the whole detector range
+    // and marches the same lines (no wave idles at the chunk barriers) while
+    // each 16-lane group reads nearly contiguous LDS entries.
     int rg[RPT], rk[RPT];
     double accd[RPT];
+    const int slot0 = (tid & 15) + 16 * ((tid >> 6) + kWaves * ((tid & 63) >> 4));
 #pragma unroll
     for (int q = 0; q < RPT; q++) {
-        const int t = tid + q * kBlock;
+        const int t = slot0 + q * kBlock;
         const bool valid = t < gcount * k_len;
         rg[q] = valid ? t / k_len : -1;
         rk[q] = valid ? k_begin + (t - rg[q] * k_len) : 0;
@@ -280,16 +265,17 @@ __global__ void __launch_bounds__(kBlock) k_ray(const float *__restrict__ x, int
         int lo = n, hi = -1;
 #pragma unroll
         for (int q = 0; q < RPT; q++) {
-            const bool act = rg[q] >= 0 && ang[rg[q] < 0 ? 0 : rg[q]].rows == pass;
-            const AngleRow &A = ang[rg[q] < 0 ? 0 : rg[q]];
+            const int gq = rg[q] < 0 ? 0 : rg[q];
+            const AngleRow &A = ang[gq];
+            const bool act = rg[q] >= 0 && A.rows == pass;
             if (act) {
                 int l0, h0;
                 ray_range(fmaf((float)rk[q], A.inv_m, A.base), A.du, n, l0, h0);
                 lo = min(lo, l0);
                 hi = max(hi, h0);
             }
-            // biased by kBias lines so that tap indices are non-negative inside
-            // the padded line; a single unsigned min then clamps both ends
+            // biased by kBias entries so that tap indices are non-negative
+            // inside the padded line; one unsigned min clamps both ends
             u[q] = act ? A.base_fx + (int64_t)rk[q] * A.inv_fx + ((int64_t)kBias << 32) : -((int64_t)1 << 44);
             du[q] = act ? A.du_fx : 0;
             facc[q] = 0.0f;
@@ -305,7 +291,7 @@ __global__ void __launch_bounds__(kBlock) k_ray(const float *__restrict__ x, int
         }
         __syncthreads();
         int blo = n, bhi = -1;
-        for (int w = 0; w < kBlock / 64; w++) {
+        for (int w = 0; w < kWaves; w++) {
             blo = min(blo, wrange[0][w]);
             bhi = max(bhi, wrange[1][w]);
         }
@@ -313,60 +299,104 @@ __global__ void __launch_bounds__(kBlock) k_ray(const float *__restrict__ x, int
         for (int q = 0; q < RPT; q++) u[q] += (int64_t)lo * du[q];   // position at the wave's first line
 
         const bool rows = pass == 1;
-        const int lo_clip = PAIRS ? -1 : 0;
+        // column passes read rows of the transposed image when it is given
+        const bool dma_rows = rows || xT != nullptr;
+        const float *src = rows || !xT ? img : xT + (size_t)b * n * n;
         const int k_last = k_begin + k_len - 1;
-        for (int c = (blo <= bhi ? blo / R : 1), c_last = (blo <= bhi ? bhi / R : 0); c <= c_last; c++) {
-            const int M0 = c * R, Rc = min(R, n - M0);
-            int cl, W;
-            chunk_span(ang, gcount, pass, k_begin, k_last, M0, Rc, n, lo_clip, cl, W);
+        if (blo <= bhi) {
+            const int c_first = blo / R, c_last = bhi / R;
+            {
+                const int M0 = c_first * R, Rc = min(R, n - M0);
+                int cl, W;
+                chunk_span(ang, gcount, pass, k_begin, k_last, M0, Rc, n, cl, W);
+                stage_dma(lds, pitch, src, n, dma_rows, M0, Rc, cl, W);
+                dma_wait();
+            }
             __syncthreads();
-            stage<PAIRS>(lds, stride, img, n, rows, M0, Rc, cl, W);
-            __syncthreads();
-            const int lb = max(lo, M0), le = min(hi, M0 + Rc - 1);
-            for (int M = lb; M <= le; M++) {
-                // entry j of the line sits at index j + kBias of `line`
-                const Entry *line = lds + (M - M0) * stride + kLinePad - kBias;
-#pragma unroll
-                for (int q = 0; q < RPT; q++) {
-                    const unsigned jb = min((unsigned)(int)(u[q] >> 32), (unsigned)(n + 1 + kBias));
-                    const float fr = (float)(uint32_t)u[q];
-                    u[q] += du[q];
-                    if constexpr (KIND == kFwd) {
-                        const float2 e = line[jb];
-                        facc[q] += e.x;
-                        facc[q] = fmaf(fr, e.y, facc[q]);
-                    } else {
-                        const float *e = line + jb;
-                        const float gq = fr * wg[q];
-                        const float wa = fmaxf(c1[q] - gq, 0.0f);   // j0-1: 1 - w (1 + f)
-                        const float wb = 1.0f - gq;                 // j0  : 1 - w f
-                        const float wc = c1[q] + gq;                // j0+1: 1 - w (1 - f)
-                        const float wd = fmaxf(c2[q] + gq, 0.0f);   // j0+2: 1 - w (2 - f)
-                        float ls = wa * e[-1];
-                        ls = fmaf(wb, e[0], ls);
-                        ls = fmaf(wc, e[1], ls);
-                        ls = fmaf(wd, e[2], ls);
-                        accd[q] += (double)ls;
-                    }
+            int cur = 0;
+            for (int c = c_first; c <= c_last; c++) {
+                const int M0 = c * R, Rc = min(R, n - M0);
+                if (c < c_last) {                 // next chunk streams in while this one is marched
+                    const int M1 = M0 + R, Rc1 = min(R, n - M1);
+                    int cl, W;
+                    chunk_span(ang, gcount, pass, k_begin, k_last, M1, Rc1, n, cl, W);
+                    stage_dma(lds + (cur ^ 1) * buf_stride, pitch, src, n, dma_rows, M1, Rc1, cl, W);
                 }
-                if constexpr (KIND == kFwd) {
-                    // float partial sums over fixed, aligned 16-line blocks: the
-                    // rounding does not depend on chunking, grouping or splits
-                    if ((M & 15) == 15) {
+                const float *chunk = lds + cur * buf_stride;
+                const int lb = max(lo, M0), le = min(hi, M0 + Rc - 1);
+                if (lb <= le) {
+                    // Software pipeline: the taps of line M+1 are read from LDS
+                    // while line M is accumulated.
+                    constexpr int NT = KIND == kFwd ? 2 : 4;   // taps per line
+                    float ta[RPT][NT], fa[RPT];
+                    auto fetch = [&](int M, float (&t)[RPT][NT], float (&f)[RPT]) {
+                        // entry j of the line sits at index j + kBias of `line`
+                        const float *line = chunk + (M - M0) * pitch + kLinePad - kBias;
 #pragma unroll
                         for (int q = 0; q < RPT; q++) {
-                            accd[q] += (double)facc[q];
-                            facc[q] = 0.0f;
+                            const unsigned jb = min((unsigned)(int)(u[q] >> 32), (unsigned)(n + 1 + kBias));
+                            f[q] = (float)(uint32_t)u[q];
+                            u[q] += du[q];
+                            const float *e = line + jb - (KIND == kFwd ? 0 : 1);
+#pragma unroll
+                            for (int t2 = 0; t2 < NT; t2++) t[q][t2] = e[t2];
                         }
+                    };
+                    // Two register sets alternate (A: even steps, B: odd steps),
+                    // so the pipeline needs no register copies.
+                    auto accumulate = [&](int M, const float (&t)[RPT][NT], const float (&f)[RPT]) {
+#pragma unroll
+                        for (int q = 0; q < RPT; q++) {
+                            if constexpr (KIND == kFwd) {
+                                facc[q] += t[q][0];
+                                facc[q] = fmaf(f[q] * kTwoM32, t[q][1] - t[q][0], facc[q]);
+                            } else {
+                                const float gq = f[q] * wg[q];
+                                const float wa = fmaxf(c1[q] - gq, 0.0f);   // j0-1: 1 - w (1 + f)
+                                const float wb = 1.0f - gq;                 // j0  : 1 - w f
+                                const float wc = c1[q] + gq;                // j0+1: 1 - w (1 - f)
+                                const float wd = fmaxf(c2[q] + gq, 0.0f);   // j0+2: 1 - w (2 - f)
+                                float ls = wa * t[q][0];
+                                ls = fmaf(wb, t[q][1], ls);
+                                ls = fmaf(wc, t[q][2], ls);
+                                ls = fmaf(wd, t[q][3], ls);
+                                accd[q] += (double)ls;
+                            }
+                        }
+                        if constexpr (KIND == kFwd) {
+                            // float partial sums over fixed, aligned 16-line blocks: the
+                            // rounding does not depend on chunking, grouping or splits
+                            if ((M & 15) == 15) {
+#pragma unroll
+                                for (int q = 0; q < RPT; q++) {
+                                    accd[q] += (double)facc[q];
+                                    facc[q] = 0.0f;
+                                }
+                            }
+                        }
+                    };
+                    float tb[RPT][NT], fb[RPT];
+                    fetch(lb, ta, fa);
+                    for (int M = lb;;) {
+                        if (M + 1 <= le) fetch(M + 1, tb, fb);
+                        accumulate(M, ta, fa);
+                        if (++M > le) break;
+                        if (M + 1 <= le) fetch(M + 1, ta, fa);
+                        accumulate(M, tb, fb);
+                        if (++M > le) break;
                     }
                 }
+                dma_wait();
+                __syncthreads();
+                cur ^= 1;
             }
+        } else {
+            __syncthreads();
         }
         if constexpr (KIND == kFwd) {
 #pragma unroll
             for (int q = 0; q < RPT; q++) accd[q] += (double)facc[q];
         }
-        __syncthreads();
     }
 
     double ss = 0.0;
@@ -396,23 +426,23 @@ __global__ void __launch_bounds__(kBlock) k_ray(const float *__restrict__ x, int
         __syncthreads();
         if (tid == 0) {
             double s = 0.0;
-            for (int w = 0; w < kBlock / 64; w++) s += red[w];
+            for (int w = 0; w < kWaves; w++) s += red[w];
             partial[item] = s;
         }
     }
 }
 
 template <int KIND, int MODE, typename OUT>
-int ray_launch(const Plan &p, hipStream_t st, const float *x, int n, int n_det, const int32_t *idx, int m,
-               const AngleRow *tab, OUT *y, const float *yfull, int n_angles, double *partial)
+int ray_launch(const Plan &p, hipStream_t st, const float *x, const float *xT, int n, int n_det, const int32_t *idx,
+               int m, const AngleRow *tab, OUT *y, const float *yfull, int n_angles, double *partial)
 {
     const long long per = (p.total + 7) / 8;
     if (8 * per > 0x7fffffffLL) return SKEI_ERANGE;
     const dim3 grid((unsigned)(8 * per)), block(kBlock);
 #define SKEI_RAY_CASE(P)                                                                                       \
     case P:                                                                                                    \
-        hipLaunchKernelGGL((k_ray<KIND, P, MODE, OUT>), grid, block, p.shm, st, x, n, n_det, idx, m, tab, p.G, \
-                           p.nseg, p.seg, p.ngroups, p.total, p.R, p.stride, y, yfull, n_angles, partial);     \
+        hipLaunchKernelGGL((k_ray<KIND, P, MODE, OUT>), grid, block, p.shm, st, x, xT, n, n_det, idx, m, tab, p.G, \
+                           p.nseg, p.seg, p.ngroups, p.total, p.R, p.pitch, y, yfull, n_angles, partial);      \
         break;
     switch (p.rpt) {
         SKEI_RAY_CASE(1)
@@ -434,33 +464,33 @@ int ray_launch(const Plan &p, hipStream_t st, const float *x, int n, int n_det, 
 size_t radon_fwd_partials(const skei_geom *g, int batch, int m, const RayTune &tune)
 {
     Plan p;
-    if (make_plan(g, batch, m, tune, sizeof(float2), p) != SKEI_OK) return 0;
+    if (make_plan(g, batch, m, tune, p) != SKEI_OK) return 0;
     return (size_t)p.total;
 }
 
-int launch_radon_fwd(const skei_geom *g, const float *x, int batch, const int32_t *idx, int m, float *y,
-                     const float *yfull, double *partial, const RayTune &tune, hipStream_t st)
+int launch_radon_fwd(const skei_geom *g, const float *x, const float *xT, int batch, const int32_t *idx, int m,
+                     float *y, const float *yfull, double *partial, const RayTune &tune, hipStream_t st)
 {
     Plan p;
-    int rc = make_plan(g, batch, m, tune, sizeof(float2), p);
+    int rc = make_plan(g, batch, m, tune, p);
     if (rc) return rc;
     if (yfull)
-        return ray_launch<kFwd, kResidSub, float>(p, st, x, g->n, g->n_det, idx, m, g->tab, y, yfull, g->n_angles,
-                                                  partial);
-    return ray_launch<kFwd, kPlain, float>(p, st, x, g->n, g->n_det, idx, m, g->tab, y, nullptr, g->n_angles,
+        return ray_launch<kFwd, kResidSub, float>(p, st, x, xT, g->n, g->n_det, idx, m, g->tab, y, yfull,
+                                                  g->n_angles, partial);
+    return ray_launch<kFwd, kPlain, float>(p, st, x, xT, g->n, g->n_det, idx, m, g->tab, y, nullptr, g->n_angles,
                                            nullptr);
 }
 
-int launch_bp_T(const skei_geom *g, const float *x, int batch, const int32_t *idx, int m, float *qf, double *qd,
-                const RayTune &tune, hipStream_t st)
+int launch_bp_T(const skei_geom *g, const float *x, const float *xT, int batch, const int32_t *idx, int m, float *qf,
+                double *qd, const RayTune &tune, hipStream_t st)
 {
     Plan p;
-    int rc = make_plan(g, batch, m, tune, sizeof(float), p);
+    int rc = make_plan(g, batch, m, tune, p);
     if (rc) return rc;
     if (qd)
-        return ray_launch<kBpT, kPlain, double>(p, st, x, g->n, g->n_det, idx, m, g->tab, qd, nullptr, g->n_angles,
-                                                nullptr);
-    return ray_launch<kBpT, kPlain, float>(p, st, x, g->n, g->n_det, idx, m, g->tab, qf, nullptr, g->n_angles,
+        return ray_launch<kBpT, kPlain, double>(p, st, x, xT, g->n, g->n_det, idx, m, g->tab, qd, nullptr,
+                                                g->n_angles, nullptr);
+    return ray_launch<kBpT, kPlain, float>(p, st, x, xT, g->n, g->n_det, idx, m, g->tab, qf, nullptr, g->n_angles,
                                            nullptr);
 }
 

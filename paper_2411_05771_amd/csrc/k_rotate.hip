@@ -39,30 +39,56 @@ __device__ __forceinline__ Sample sample_point(int i, int j, float c, float s, d
     return r;
 }
 
+// One 16 x 16 output tile per workgroup; the tile is also written transposed
+// (through LDS, so both stores are coalesced) when outT is given.
 __global__ void __launch_bounds__(256) k_rotate(const float *__restrict__ x, int n, int copies,
-                                                const float *__restrict__ cs, float *__restrict__ out)
+                                                const float *__restrict__ cs, float *__restrict__ out,
+                                                float *__restrict__ outT)
 {
-    const int p = blockIdx.x * 256 + threadIdx.x;
+    __shared__ float tile[16][17];
+    const int tiles_x = (n + 15) / 16;
+    const int i0 = (blockIdx.x / tiles_x) * 16, j0 = (blockIdx.x % tiles_x) * 16;
     const int bc = blockIdx.y;                 // b * copies + c
-    if (p >= n * n) return;
     const int b = bc / copies, c = bc - b * copies;
-    const int i = p / n, j = p - i * n;
+    const int dx = threadIdx.x & 15, dy = threadIdx.x >> 4;
+    const int i = i0 + dy, j = j0 + dx;
     const double cN = 0.5 * (double)(n - 1);
-    const Sample sp = sample_point(i, j, cs[2 * c], cs[2 * c + 1], cN);
-    const float *img = x + (size_t)b * n * n;
     float acc = 0.0f;
+    if (i < n && j < n) {
+        const Sample sp = sample_point(i, j, cs[2 * c], cs[2 * c + 1], cN);
+        const float *img = x + (size_t)b * n * n;
 #pragma unroll
-    for (int di = 0; di < 2; di++) {
-        const int ii = sp.i0 + di;
-        const float wv = di ? sp.av : 1.0f - sp.av;
+        for (int di = 0; di < 2; di++) {
+            const int ii = sp.i0 + di;
+            const float wv = di ? sp.av : 1.0f - sp.av;
 #pragma unroll
-        for (int dj = 0; dj < 2; dj++) {
-            const int jj = sp.j0 + dj;
-            const float wu = dj ? sp.au : 1.0f - sp.au;
-            if (ii >= 0 && ii < n && jj >= 0 && jj < n) acc = fmaf(wv * wu, img[(size_t)ii * n + jj], acc);
+            for (int dj = 0; dj < 2; dj++) {
+                const int jj = sp.j0 + dj;
+                const float wu = dj ? sp.au : 1.0f - sp.au;
+                if (ii >= 0 && ii < n && jj >= 0 && jj < n) acc = fmaf(wv * wu, img[(size_t)ii * n + jj], acc);
+            }
         }
+        out[(size_t)bc * n * n + (size_t)i * n + j] = acc;
     }
-    out[(size_t)bc * n * n + p] = acc;
+    if (outT) {
+        tile[dy][dx] = acc;
+        __syncthreads();
+        const int it = j0 + dy, jt = i0 + dx;   // transposed position: row = original column
+        if (it < n && jt < n) outT[(size_t)bc * n * n + (size_t)it * n + jt] = tile[dx][dy];
+    }
+}
+
+// xT[b][j][i] = x[b][i][j], 16 x 16 tiles through LDS.
+__global__ void __launch_bounds__(256) k_transpose(const float *__restrict__ x, int n, float *__restrict__ xT)
+{
+    __shared__ float tile[16][17];
+    const int tiles_x = (n + 15) / 16;
+    const int i0 = (blockIdx.x / tiles_x) * 16, j0 = (blockIdx.x % tiles_x) * 16;
+    const size_t off = (size_t)blockIdx.y * n * n;
+    const int dx = threadIdx.x & 15, dy = threadIdx.x >> 4;
+    if (i0 + dy < n && j0 + dx < n) tile[dy][dx] = x[off + (size_t)(i0 + dy) * n + j0 + dx];
+    __syncthreads();
+    if (j0 + dy < n && i0 + dx < n) xT[off + (size_t)(j0 + dy) * n + i0 + dx] = tile[dx][dy];
 }
 
 // g[b][p'] = alpha * sum_c sum_p T_c[p][p'] h[b][c][p] + beta * add[b][p']
@@ -123,10 +149,20 @@ __global__ void __launch_bounds__(256) k_rotate_adj(const float *__restrict__ h,
 
 }  // namespace
 
-int launch_rotate(const float *x, int batch, int copies, int n, const float *cs, float *out, hipStream_t st)
+int launch_rotate(const float *x, int batch, int copies, int n, const float *cs, float *out, hipStream_t st,
+                  float *outT)
 {
-    const dim3 grid((n * n + 255) / 256, batch * copies);
-    hipLaunchKernelGGL(k_rotate, grid, dim3(256), 0, st, x, n, copies, cs, out);
+    const int t = (n + 15) / 16;
+    const dim3 grid(t * t, batch * copies);
+    hipLaunchKernelGGL(k_rotate, grid, dim3(256), 0, st, x, n, copies, cs, out, outT);
+    return check_launch();
+}
+
+int launch_transpose(const float *x, int batch, int n, float *xT, hipStream_t st)
+{
+    const int t = (n + 15) / 16;
+    const dim3 grid(t * t, batch);
+    hipLaunchKernelGGL(k_transpose, grid, dim3(256), 0, st, x, n, xT);
     return check_launch();
 }
 

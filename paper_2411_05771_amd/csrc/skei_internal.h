@@ -64,13 +64,19 @@ struct RayTune {
 //   plain:   y[b][r][k] = (A_S x[b])[r][k]
 //   resid:   y[b][r][k] = yfull[b][idx[r]][k] - (A_S x[b])[r][k]  (difference taken in double);
 //            partial[] = per-workgroup sums of y^2
-int launch_radon_fwd(const skei_geom *g, const float *x, int batch, const int32_t *idx, int m, float *y,
-                     const float *yfull, double *partial, const RayTune &tune, hipStream_t st);
+// xT (optional, may be null): the images transposed, [batch][N][N] with
+// xT[b][j][i] = x[b][i][j]; when given, column-stepping angles stage rows of xT
+// (contiguous DMA) instead of gathering columns of x.
+int launch_radon_fwd(const skei_geom *g, const float *x, const float *xT, int batch, const int32_t *idx, int m,
+                     float *y, const float *yfull, double *partial, const RayTune &tune, hipStream_t st);
 size_t radon_fwd_partials(const skei_geom *g, int batch, int m, const RayTune &tune);
 
 // Ray-driven B_S^T (unscaled), written as float (qf) or double (qd; exactly one non-null).
-int launch_bp_T(const skei_geom *g, const float *x, int batch, const int32_t *idx, int m, float *qf,
-                double *qd, const RayTune &tune, hipStream_t st);
+int launch_bp_T(const skei_geom *g, const float *x, const float *xT, int batch, const int32_t *idx, int m,
+                float *qf, double *qd, const RayTune &tune, hipStream_t st);
+
+// xT[b] = transpose(x[b]) for square N x N images.
+int launch_transpose(const float *x, int batch, int n, float *xT, hipStream_t st);
 
 // Pixel-driven gathers over the listed angles.
 //   joseph: A_S^T y   ;  bp: scale * B_S q
@@ -78,7 +84,8 @@ int launch_bp_T(const skei_geom *g, const float *x, int batch, const int32_t *id
 int launch_radon_adj(const skei_geom *g, const float *y, int batch, const int32_t *idx, int m,
                      float *x, const float *other, hipStream_t st);
 int launch_backproject(const skei_geom *g, const float *q, int batch, const int32_t *idx, int m,
-                       float scale, float *x, const float *other, double *partial, hipStream_t st);
+                       float scale, float *x, const float *other, double *partial, hipStream_t st,
+                       float *xT = nullptr);
 size_t gather_partials(const skei_geom *g, int batch);
 
 // Ram-Lak ramp along rows, double accumulation, times `scale`; the input is
@@ -88,7 +95,9 @@ int launch_ramp(const skei_geom *g, const float *pf, const double *pd, int rows,
 
 // Rotation and its transpose (copies summed).  rotate_adj optionally fuses
 // g = alpha * sum_c T_c^T h[b][c] + beta * add[b].
-int launch_rotate(const float *x, int batch, int copies, int n, const float *cs, float *out, hipStream_t st);
+// outT (optional): also write every output image transposed.
+int launch_rotate(const float *x, int batch, int copies, int n, const float *cs, float *out, hipStream_t st,
+                  float *outT = nullptr);
 int launch_rotate_adj(const float *h, int batch, int copies, int n, const float *cs, float alpha,
                       const float *add, float beta, float *g, hipStream_t st);
 
@@ -104,6 +113,7 @@ int launch_reduce2(const double *p0, size_t n0, double w0, const double *p1, siz
 struct skei_geom {
     int n, n_angles, n_det;
     int device;
+    skei::RayTune tune_fwd, tune_bpt;
     skei::AngleRow *tab;   // device [n_angles]
     double *hodd;          // device [n_hodd]: h(2e+1) = -1 / (pi (2e+1))^2
     int n_hodd;
