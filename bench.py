@@ -60,14 +60,12 @@ def algorithmic_flops(stage, w, widths):
     n, nd, c, m, b = w["n"], w["n_det"], w["copies"], w["m"], w["batch"]
     na = w["n_angles"]
     bc = b * c
-    if stage == "fwd_sketch":          # Joseph: 2 taps per major-axis line per ray
-        return 2.0 * (2 * n) * bc * m * nd
-    if stage == "fwd_mc":
-        return 2.0 * (2 * n) * b * na * nd
-    if stage in ("adj_sketch", "bp_resid"):   # 2 taps per (pixel, angle)
+    if stage == "fwd":                 # Joseph: 2 taps per major-axis line per ray (A_S on copies + A_mc)
+        return 2.0 * (2 * n) * (bc * m + b * na) * nd
+    if stage == "adj":                 # 2 taps per (pixel, angle): A_S^T on copies + A_mc^T
+        return 2.0 * 2 * n * n * (bc * m + b * na)
+    if stage == "bp_resid":
         return 2.0 * 2 * n * n * bc * m
-    if stage == "adj_mc":
-        return 2.0 * 2 * n * n * b * na
     if stage == "bp_T":                # 2/w pixels within unit distance per line, per ray
         return 2.0 * n * nd * bc * float(np.sum(2.0 / widths))
     if stage in ("ramp", "ramp_T"):    # symmetric form: one multiply-add per odd offset pair + centre

@@ -171,15 +171,84 @@ int skei_ei_loss_grad(const skei_geom *g, const float *x, const float *y, int ba
                       int copies, const float *cos_sin, float lambda,
                       double *loss, float *grad, void *work, size_t work_bytes, void *stream);
 
-/* Profiling probe for skei_ei_loss_grad: when set, the next calls record
- * hipEvent_t `ev_begin` / `ev_end` on their stream immediately before and
- * after the launch of stage `stage` (SKEI_STAGE_*), so a caller can time one
- * kernel inside the fused step with hipEventElapsedTime.  Pass stage < 0 (or
- * null events) to clear.  Process-wide setting; not for concurrent callers. */
+/* ------------------------------------------------------------------ */
+/* Batched EI plans: many EI problems of different sizes (own geometry, */
+/* batch, sketch, copies) evaluated together, one launch per stage for  */
+/* all of them.  Each problem computes exactly what skei_ei_loss_grad   */
+/* computes for it, bitwise: results do not depend on the other         */
+/* problems, the dispatch mode or the launch shapes.                    */
+/*                                                                      */
+/* A plan binds the problems' device pointers and a caller workspace of */
+/* skei_ei_plan_workspace_bytes() bytes at creation; it owns a small    */
+/* device table (work lists and queue cursors) that destroy frees.      */
+/* Runs of one plan must not overlap (they share the queue cursors);    */
+/* different plans may run concurrently on different streams.  Problems */
+/* with grad == NULL get the loss only.                                 */
+/* ------------------------------------------------------------------ */
+typedef struct skei_ei_problem {
+    const skei_geom *geom;
+    int batch;
+    const float *x;             /* [batch][N][N]                         */
+    const float *y;             /* [batch][N_theta][N_det]               */
+    const int32_t *mc_idx;      /* MC angle list, m_mc entries           */
+    int m_mc;
+    const int32_t *angle_idx;   /* sketch, m entries                     */
+    int m;
+    int copies;
+    const float *cos_sin;       /* [copies][2]                           */
+    float lambda;
+    double *loss;               /* one device double                     */
+    float *grad;                /* [batch][N][N] or NULL                 */
+} skei_ei_problem;
+
+typedef struct skei_ei_plan skei_ei_plan;
+
+size_t skei_ei_plan_workspace_bytes(const skei_ei_problem *problems, int count);
+int skei_ei_plan_create(const skei_ei_problem *problems, int count, void *work, size_t work_bytes,
+                        skei_ei_plan **out);
+int skei_ei_plan_destroy(skei_ei_plan *plan);
+int skei_ei_plan_run(skei_ei_plan *plan, void *stream);
+
+/* Dispatch of one stage (SKEI_STAGE_*) of a plan:
+ *   SKEI_DISPATCH_PERSISTENT: one resident wave of workgroups that draw work
+ *     items from per-XCD queues, then steal from the other XCDs' queues;
+ *   SKEI_DISPATCH_STATIC: one workgroup per work item, XCD-major ranges.
+ * `shape`: rays per thread (1..8) for the ray-driven stages (FWD, BP_T),
+ * angle groups per pixel (1, 2, 4) for the gathers (BP_RESID, ADJ); 0 keeps
+ * the default; ignored by the other stages.  Synchronises the device when
+ * the shape changes (the work list is rebuilt). */
+enum { SKEI_DISPATCH_PERSISTENT = 0, SKEI_DISPATCH_STATIC = 1 };
+int skei_ei_plan_configure(skei_ei_plan *plan, int stage, int dispatch, int shape);
+int skei_ei_plan_get_config(const skei_ei_plan *plan, int stage, int *dispatch, int *shape);
+
+/* Autotuner: for every stage, times each (dispatch, shape) candidate on the
+ * plan's own problems (hipEvents, median of `reps` launches on `stream`) and
+ * keeps the fastest.  Choices are cached per stage under a signature of the
+ * stage's work list (sizes, not pointers) -- in memory, and in the text file
+ * `cache_path` when it is not NULL (read first, appended to).  The plan must
+ * have been run once (its buffers hold finite values).  Synchronises. */
+int skei_ei_plan_autotune(skei_ei_plan *plan, void *stream, int reps, const char *cache_path);
+
+/* Profiling probe for skei_ei_loss_grad and skei_ei_plan_run: when set, the
+ * next calls record hipEvent_t `ev_begin` / `ev_end` on their stream
+ * immediately before and after the launch of stage `stage` (SKEI_STAGE_*),
+ * so a caller can time one kernel inside the fused step with
+ * hipEventElapsedTime.  Pass stage < 0 (or null events) to clear.
+ * Process-wide setting; not for concurrent callers.
+ * Stages of one EI step, in launch order:
+ *   ROTATE     z = T x (and z^T), x^T
+ *   FWD        A_S z and the MC residual y[mc] - A_mc x (one launch)
+ *   RAMP       H A_S z
+ *   BP_RESID   r = z - (pi/m) B_S H A_S z
+ *   REDUCE     the loss
+ *   BP_T       B_S^T r
+ *   RAMP_T     (pi/m) H B_S^T r
+ *   ADJ        r - A_S^T (...) and A_mc^T r_MC (one launch)
+ *   ROTATE_ADJ the gradient */
 enum {
-    SKEI_STAGE_ROTATE = 0, SKEI_STAGE_FWD_SKETCH = 1, SKEI_STAGE_RAMP = 2, SKEI_STAGE_BP_RESID = 3,
-    SKEI_STAGE_FWD_MC = 4, SKEI_STAGE_REDUCE = 5, SKEI_STAGE_BP_T = 6, SKEI_STAGE_RAMP_T = 7,
-    SKEI_STAGE_ADJ_SKETCH = 8, SKEI_STAGE_ADJ_MC = 9, SKEI_STAGE_ROTATE_ADJ = 10, SKEI_STAGE_COUNT = 11
+    SKEI_STAGE_ROTATE = 0, SKEI_STAGE_FWD = 1, SKEI_STAGE_RAMP = 2, SKEI_STAGE_BP_RESID = 3,
+    SKEI_STAGE_REDUCE = 4, SKEI_STAGE_BP_T = 5, SKEI_STAGE_RAMP_T = 6, SKEI_STAGE_ADJ = 7,
+    SKEI_STAGE_ROTATE_ADJ = 8, SKEI_STAGE_COUNT = 9
 };
 int skei_probe_set(int stage, void *ev_begin, void *ev_end);
 

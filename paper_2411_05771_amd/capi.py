@@ -24,6 +24,18 @@ _lib = None
 c_int, c_float, c_size_t, c_void_p, c_double = ctypes.c_int, ctypes.c_float, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_double
 c_char_p = ctypes.c_char_p
 
+
+class EiProblem(ctypes.Structure):
+    """skei_ei_problem (include/skei_ct.h); pointers are device addresses."""
+    _fields_ = [
+        ("geom", c_void_p), ("batch", c_int), ("x", c_void_p), ("y", c_void_p),
+        ("mc_idx", c_void_p), ("m_mc", c_int), ("angle_idx", c_void_p), ("m", c_int),
+        ("copies", c_int), ("cos_sin", c_void_p), ("lam", c_float), ("loss", c_void_p), ("grad", c_void_p),
+    ]
+
+
+_PROB = ctypes.POINTER(EiProblem)
+
 # name -> (restype, argtypes); every pointer is passed as void*.
 _SIGS = {
     "skei_version": (c_char_p, []),
@@ -48,6 +60,13 @@ _SIGS = {
     "skei_probe_set": (c_int, [c_int, c_void_p, c_void_p]),
     "skei_ei_loss_grad": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_int, c_void_p, c_int,
                                   c_int, c_void_p, c_float, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "skei_ei_plan_workspace_bytes": (c_size_t, [_PROB, c_int]),
+    "skei_ei_plan_create": (c_int, [_PROB, c_int, c_void_p, c_size_t, ctypes.POINTER(c_void_p)]),
+    "skei_ei_plan_destroy": (c_int, [c_void_p]),
+    "skei_ei_plan_run": (c_int, [c_void_p, c_void_p]),
+    "skei_ei_plan_configure": (c_int, [c_void_p, c_int, c_int, c_int]),
+    "skei_ei_plan_get_config": (c_int, [c_void_p, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
+    "skei_ei_plan_autotune": (c_int, [c_void_p, c_void_p, c_int, c_char_p]),
 }
 
 
@@ -57,8 +76,9 @@ class SkeiError(RuntimeError):
         self.code = code
 
 
-STAGES = ["rotate", "fwd_sketch", "ramp", "bp_resid", "fwd_mc", "reduce", "bp_T", "ramp_T",
-          "adj_sketch", "adj_mc", "rotate_adj"]
+# Stages of one EI step in launch order (SKEI_STAGE_*).
+STAGES = ["rotate", "fwd", "ramp", "bp_resid", "reduce", "bp_T", "ramp_T", "adj", "rotate_adj"]
+DISPATCH_PERSISTENT, DISPATCH_STATIC = 0, 1
 
 
 def exported_symbols() -> list[str]:

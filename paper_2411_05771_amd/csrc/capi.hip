@@ -1,8 +1,10 @@
 // C ABI entry points (include/skei_ct.h): argument validation, workspace
 // carving and kernel launch sequences.  Nothing here allocates device memory.
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
+#include "ei_step.h"
 #include "skei_internal.h"
 
 using namespace skei;
@@ -12,8 +14,6 @@ namespace {
 constexpr double kPi = 3.14159265358979323846;
 
 inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
-
-inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 int check_geom_op(const skei_geom *g, const void *in, int batch, const int32_t *idx, int m, const void *out)
 {
@@ -43,8 +43,34 @@ struct Carver {
     }
 };
 
+struct Probe {
+    int stage = -1;
+    hipEvent_t b = nullptr, e = nullptr;
+};
+Probe g_probe;
+
+}  // namespace
+
+namespace skei {
+
+int probe_begin(int stage, hipStream_t st)
+{
+    const bool on = g_probe.stage == stage && g_probe.b && g_probe.e;
+    if (on && hipEventRecord(g_probe.b, st) != hipSuccess) return SKEI_ELAUNCH;
+    return SKEI_OK;
+}
+
+int probe_end(int stage, hipStream_t st)
+{
+    const bool on = g_probe.stage == stage && g_probe.b && g_probe.e;
+    if (on && hipEventRecord(g_probe.e, st) != hipSuccess) return SKEI_ELAUNCH;
+    return SKEI_OK;
+}
+
+namespace {
+
 struct EiSizes {
-    size_t img, sino, mc, part_mc, part_ei, total;
+    size_t img, sino, mc, part_mc, part_ei;
 };
 
 EiSizes ei_sizes(const skei_geom *g, int batch, int m_mc, int m, int copies)
@@ -55,38 +81,97 @@ EiSizes ei_sizes(const skei_geom *g, int batch, int m_mc, int m, int copies)
     s.img = bc * nn;
     s.sino = bc * (size_t)m * g->n_det;
     s.mc = (size_t)batch * m_mc * g->n_det;
-    s.part_mc = radon_fwd_partials(g, batch, m_mc, g->tune_fwd);
-    s.part_ei = gather_partials(g, (int)bc);
-    s.total = align256(s.img * 4) * 4            // z (later d), zT, r, rT
-              + align256(nn * batch * 4)         // xT
-              + align256(s.sino * 8)             // ys (A_S z as float, later B_S^T r as double)
-              + align256(s.sino * 4)             // qs (H ys, later (pi/m) H B_S^T r)
-              + align256(s.mc * 4)               // r_MC
-              + align256(nn * batch * 4)         // A_mc^T r_MC
-              + align256(s.part_mc * 8) + align256(s.part_ei * 8);
+    s.part_mc = ray_items_max(g, batch, m_mc, g->tune_fwd);
+    s.part_ei = gather_items(g->n, (int)bc);
     return s;
 }
 
-struct Probe {
-    int stage = -1;
-    hipEvent_t b = nullptr, e = nullptr;
-};
-Probe g_probe;
+}  // namespace
 
-// Launch stage `stage` of the EI step through `fn`, bracketed by the probe's
-// events when the probe targets it.
-template <typename F>
-int staged(int stage, hipStream_t st, F &&fn)
+size_t ei_workspace_bytes(const skei_geom *g, int batch, int m_mc, int m, int copies)
 {
-    const bool on = g_probe.stage == stage && g_probe.b && g_probe.e;
-    if (on && hipEventRecord(g_probe.b, st) != hipSuccess) return SKEI_ELAUNCH;
-    const int rc = fn();
-    if (rc) return rc;
-    if (on && hipEventRecord(g_probe.e, st) != hipSuccess) return SKEI_ELAUNCH;
+    const EiSizes s = ei_sizes(g, batch, m_mc, m, copies);
+    const size_t nn = (size_t)g->n * g->n;
+    return align256(s.img * 4) * 4          // z (later d), zT, r, rT
+           + align256(nn * batch * 4)       // xT
+           + align256(s.sino * 8)           // ys (A_S z as float, later B_S^T r as double)
+           + align256(s.sino * 4)           // qs (H ys, later (pi/m) H B_S^T r)
+           + align256(s.mc * 4)             // r_MC
+           + align256(nn * batch * 4)       // A_mc^T r_MC
+           + align256(s.part_mc * 8) + align256(s.part_ei * 8);
+}
+
+bool ei_carve(const skei_geom *g, int batch, int m_mc, int m, int copies, void *work, size_t bytes, EiBuffers &b)
+{
+    const EiSizes sz = ei_sizes(g, batch, m_mc, m, copies);
+    const size_t nn = (size_t)g->n * g->n;
+    Carver cv{static_cast<char *>(work), bytes};
+    b.z = cv.take<float>(sz.img);
+    b.zT = cv.take<float>(sz.img);
+    b.r = cv.take<float>(sz.img);
+    b.rT = cv.take<float>(sz.img);
+    b.xT = cv.take<float>(nn * batch);
+    b.ysd = cv.take<double>(sz.sino);
+    b.ys = reinterpret_cast<float *>(b.ysd);
+    b.qs = cv.take<float>(sz.sino);
+    b.rmc = cv.take<float>(sz.mc);
+    b.amc = cv.take<float>(nn * batch);
+    b.pmc = cv.take<double>(sz.part_mc);
+    b.pei = cv.take<double>(sz.part_ei);
+    b.n_pmc = sz.part_mc;
+    b.n_pei = sz.part_ei;
+    return cv.ok;
+}
+
+int ei_problem_jobs(const skei_ei_problem &p, const EiBuffers &b, int fwd_rpt, int bpt_rpt, EiJobs &J)
+{
+    const skei_geom *g = p.geom;
+    const int n = g->n, batch = p.batch, copies = p.copies, m = p.m, m_mc = p.m_mc;
+    const int bc = batch * copies;
+    const float pim = (float)(kPi / m);
+    int rc;
+    // forward: z = T x ; ys = A_S z ; r_MC = y[mc] - A_mc x ; qs = H ys ;
+    //          r = z - (pi/m) B_S qs ; loss
+    J.rot[0] = make_rot_job(p.x, batch, copies, n, p.cos_sin, b.z, b.zT);
+    J.rot[1] = make_rot_job(p.x, batch, 1, n, nullptr, nullptr, b.xT);
+    if ((rc = make_ray_job(g, b.z, b.zT, bc, p.angle_idx, m, b.ys, nullptr, nullptr, g->tune_fwd, fwd_rpt, J.fwd[0],
+                           J.fwd_shape[0])))
+        return rc;
+    // The MC residual's sums of squares are per work item, so its items take
+    // one fixed shape (one angle, segments of at most 512 detectors) whatever
+    // the tuning: the loss is then bitwise the same under every launch shape.
+    RayTune mc_shape;
+    mc_shape.group = 1;
+    mc_shape.split = (g->n_det + 511) / 512;
+    if ((rc = make_ray_job(g, p.x, b.xT, batch, p.mc_idx, m_mc, b.rmc, p.y, b.pmc, mc_shape, 0, J.fwd[1],
+                           J.fwd_shape[1])))
+        return rc;
+    if ((size_t)J.fwd[1].items > b.n_pmc) return SKEI_ERANGE;
+    J.ramp = make_ramp_job(g, b.ys, (long long)bc * m, 1.0f, b.qs);
+    J.bp = make_gather_job(g, b.qs, bc, p.angle_idx, m, pim, b.r, b.z, b.pei, b.rT);
+    J.red = RedJob{};
+    J.red.p0 = b.pmc;
+    J.red.n0 = J.fwd[1].items;
+    J.red.w0 = 1.0;
+    J.red.p1 = b.pei;
+    J.red.n1 = J.bp.items;
+    J.red.w1 = (double)p.lambda / copies;
+    J.red.out = p.loss;
+    J.red.items = 1;
+    // backward: ysd = B_S^T r ; qs = (pi/m) H ysd ; z = r - A_S^T qs ;
+    //           amc = A_mc^T r_MC ; grad = (2 lambda / C) sum_c T_c^T z - 2 amc
+    J.grad = p.grad != nullptr;
+    if ((rc = make_ray_job(g, b.r, b.rT, bc, p.angle_idx, m, b.ysd, nullptr, nullptr, g->tune_bpt, bpt_rpt, J.bpt,
+                           J.bpt_shape)))
+        return rc;
+    J.rampT = make_ramp_job(g, b.ysd, (long long)bc * m, pim, b.qs);
+    J.adj[0] = make_gather_job(g, b.qs, bc, p.angle_idx, m, 1.0f, b.z, b.r, nullptr, nullptr);
+    J.adj[1] = make_gather_job(g, b.rmc, batch, p.mc_idx, m_mc, 1.0f, b.amc, nullptr, nullptr, nullptr);
+    J.radj = make_rot_adj_job(b.z, batch, copies, n, p.cos_sin, 2.0f * p.lambda / copies, b.amc, -2.0f, p.grad);
     return SKEI_OK;
 }
 
-}  // namespace
+}  // namespace skei
 
 extern "C" {
 
@@ -112,7 +197,7 @@ int skei_radon_adj(const skei_geom *g, const float *y, int batch, const int32_t 
 {
     int rc = check_geom_op(g, y, batch, angle_idx, m, x);
     if (rc) return rc;
-    return launch_radon_adj(g, y, batch, angle_idx, m, x, nullptr, S(stream));
+    return launch_gather(kGatherJosephAdj, g, y, batch, angle_idx, m, 1.0f, x, nullptr, nullptr, nullptr, S(stream));
 }
 
 int skei_ramp(const skei_geom *g, const float *p, int rows, float *q, void *stream)
@@ -126,7 +211,7 @@ int skei_backproject(const skei_geom *g, const float *q, int batch, const int32_
 {
     int rc = check_geom_op(g, q, batch, angle_idx, m, x);
     if (rc) return rc;
-    return launch_backproject(g, q, batch, angle_idx, m, 1.0f, x, nullptr, nullptr, S(stream));
+    return launch_gather(kGatherBackproject, g, q, batch, angle_idx, m, 1.0f, x, nullptr, nullptr, nullptr, S(stream));
 }
 
 int skei_backproject_T(const skei_geom *g, const float *x, int batch, const int32_t *angle_idx, int m, float *q,
@@ -157,7 +242,8 @@ int skei_fbp(const skei_geom *g, const float *y, int batch, const int32_t *angle
     float *q = static_cast<float *>(work);
     rc = launch_ramp(g, y, nullptr, batch * m, 1.0f, q, S(stream));
     if (rc) return rc;
-    return launch_backproject(g, q, batch, angle_idx, m, (float)(kPi / m), x, nullptr, nullptr, S(stream));
+    return launch_gather(kGatherBackproject, g, q, batch, angle_idx, m, (float)(kPi / m), x, nullptr, nullptr, nullptr,
+                         S(stream));
 }
 
 int skei_fbp_adj(const skei_geom *g, const float *x, int batch, const int32_t *angle_idx, int m, float *y,
@@ -170,7 +256,7 @@ int skei_fbp_adj(const skei_geom *g, const float *x, int batch, const int32_t *a
     double *t = static_cast<double *>(work);
     float *xT = reinterpret_cast<float *>(static_cast<char *>(work) +
                                           align256((size_t)batch * m * g->n_det * sizeof(double)));
-    rc = launch_transpose(x, batch, g->n, xT, S(stream));
+    rc = launch_rotate(x, batch, 1, g->n, nullptr, nullptr, xT, S(stream));
     if (rc) return rc;
     rc = launch_bp_T(g, x, xT, batch, angle_idx, m, nullptr, t, g->tune_bpt, S(stream));
     if (rc) return rc;
@@ -181,7 +267,7 @@ int skei_rotate(const float *x, int batch, int copies, int n, const float *cos_s
 {
     if (!x || !cos_sin || !out || batch <= 0 || copies <= 0 || n < 2) return SKEI_EINVAL;
     if ((size_t)batch * copies > 65535 || n > 16384) return SKEI_ERANGE;
-    return launch_rotate(x, batch, copies, n, cos_sin, out, S(stream));
+    return launch_rotate(x, batch, copies, n, cos_sin, out, nullptr, S(stream));
 }
 
 int skei_rotate_adj(const float *h, int batch, int copies, int n, const float *cos_sin, float *g, void *stream)
@@ -207,7 +293,7 @@ int skei_sumsq_diff(const float *a, const float *b, size_t len, double *out, voi
 size_t skei_ei_workspace_bytes(const skei_geom *g, int batch, int m_mc, int m, int copies)
 {
     if (!g || batch <= 0 || m_mc <= 0 || m <= 0 || copies <= 0) return 0;
-    return ei_sizes(g, batch, m_mc, m, copies).total;
+    return ei_workspace_bytes(g, batch, m_mc, m, copies);
 }
 
 int skei_ei_loss_grad(const skei_geom *g, const float *x, const float *y, int batch, const int32_t *mc_idx,
@@ -217,63 +303,40 @@ int skei_ei_loss_grad(const skei_geom *g, const float *x, const float *y, int ba
     if (!g || !x || !y || !mc_idx || !angle_idx || !cos_sin || !loss || !work) return SKEI_EINVAL;
     if (batch <= 0 || m_mc <= 0 || m <= 0 || copies <= 0) return SKEI_EINVAL;
     if ((size_t)batch * copies > 65535) return SKEI_ERANGE;
-    const EiSizes sz = ei_sizes(g, batch, m_mc, m, copies);
-    if (work_bytes < sz.total) return SKEI_ESPACE;
-    Carver cv{static_cast<char *>(work), work_bytes};
-    float *z = cv.take<float>(sz.img);
-    float *zT = cv.take<float>(sz.img);
-    float *r = cv.take<float>(sz.img);
-    float *rT = cv.take<float>(sz.img);
-    float *xT = cv.take<float>((size_t)g->n * g->n * batch);
-    double *ysd = cv.take<double>(sz.sino);
-    float *ys = reinterpret_cast<float *>(ysd);
-    float *qs = cv.take<float>(sz.sino);
-    float *rmc = cv.take<float>(sz.mc);
-    float *amc = cv.take<float>((size_t)g->n * g->n * batch);
-    double *pmc = cv.take<double>(sz.part_mc);
-    double *pei = cv.take<double>(sz.part_ei);
-    if (!cv.ok) return SKEI_ESPACE;
+    EiBuffers b;
+    if (!ei_carve(g, batch, m_mc, m, copies, work, work_bytes, b)) return SKEI_ESPACE;
+    const skei_ei_problem p{g, batch, x, y, mc_idx, m_mc, angle_idx, m, copies, cos_sin, lambda, loss, grad};
+    EiJobs J;
+    int rc = ei_problem_jobs(p, b, 0, 0, J);
+    if (rc) return rc;
 
     const hipStream_t st = S(stream);
-    const int bc = batch * copies;
-    const float pim = (float)(kPi / m);
-    int rc;
-    // forward: z = T x ; ys = A_S z ; qs = H ys ; r = z - (pi/m) B_S qs ; r_MC = y[mc] - A_mc x
-    if ((rc = staged(SKEI_STAGE_ROTATE, st, [&] { return launch_rotate(x, batch, copies, g->n, cos_sin, z, st, zT); })))
+    const int fwd_rpt = std::max(J.fwd_shape[0].rpt, J.fwd_shape[1].rpt);
+    const size_t fwd_shm = std::max(J.fwd_shape[0].shm, J.fwd_shape[1].shm);
+    int rpt, block;
+    ramp_shape(g->n_det, rpt, block);
+    if ((rc = staged(SKEI_STAGE_ROTATE, st, [&] { return rotate_run(inline_jobs(J.rot, 2), st); }))) return rc;
+    if ((rc = staged(SKEI_STAGE_FWD, st, [&] { return ray_run(kRayFwd, false, fwd_rpt, fwd_shm, inline_jobs(J.fwd, 2), st); })))
         return rc;
-    if ((rc = staged(SKEI_STAGE_FWD_SKETCH, st,
-                     [&] { return launch_radon_fwd(g, z, zT, bc, angle_idx, m, ys, nullptr, nullptr, g->tune_fwd, st); })))
+    if ((rc = staged(SKEI_STAGE_RAMP, st,
+                     [&] { return ramp_run(false, rpt, block, ramp_shm(g->n_det, false), inline_jobs(&J.ramp, 1), st); })))
         return rc;
-    if ((rc = staged(SKEI_STAGE_RAMP, st, [&] { return launch_ramp(g, ys, nullptr, bc * m, 1.0f, qs, st); }))) return rc;
     if ((rc = staged(SKEI_STAGE_BP_RESID, st,
-                     [&] { return launch_backproject(g, qs, bc, angle_idx, m, pim, r, z, pei, st, rT); })))
+                     [&] { return gather_run(kGatherBackproject, gather_groups_auto(m), inline_jobs(&J.bp, 1), st); })))
         return rc;
-    if ((rc = staged(SKEI_STAGE_FWD_MC, st,
-                     [&] {
-                         int rc2 = launch_transpose(x, batch, g->n, xT, st);
-                         if (rc2) return rc2;
-                         return launch_radon_fwd(g, x, xT, batch, mc_idx, m_mc, rmc, y, pmc, g->tune_fwd, st);
-                     })))
+    if ((rc = staged(SKEI_STAGE_REDUCE, st, [&] { return reduce_run(inline_jobs(&J.red, 1), st); }))) return rc;
+    if (!grad) return SKEI_OK;
+    if ((rc = staged(SKEI_STAGE_BP_T, st,
+                     [&] { return ray_run(kRayBpT, true, J.bpt_shape.rpt, J.bpt_shape.shm, inline_jobs(&J.bpt, 1), st); })))
         return rc;
-    if ((rc = staged(SKEI_STAGE_REDUCE, st, [&] {
-             return launch_reduce2(pmc, sz.part_mc, 1.0, pei, sz.part_ei, (double)lambda / copies, loss, st);
+    if ((rc = staged(SKEI_STAGE_RAMP_T, st,
+                     [&] { return ramp_run(true, rpt, block, ramp_shm(g->n_det, true), inline_jobs(&J.rampT, 1), st); })))
+        return rc;
+    if ((rc = staged(SKEI_STAGE_ADJ, st, [&] {
+             return gather_run(kGatherJosephAdj, gather_groups_auto(std::max(m, m_mc)), inline_jobs(J.adj, 2), st);
          })))
         return rc;
-    if (!grad) return SKEI_OK;
-    // backward: ys = B_S^T r ; qs = (pi/m) H ys ; z = r - A_S^T qs ;
-    //           amc = A_mc^T r_MC ; grad = (2 lambda / C) sum_c T_c^T z - 2 amc
-    if ((rc = staged(SKEI_STAGE_BP_T, st, [&] { return launch_bp_T(g, r, rT, bc, angle_idx, m, nullptr, ysd, g->tune_bpt, st); })))
-        return rc;
-    if ((rc = staged(SKEI_STAGE_RAMP_T, st, [&] { return launch_ramp(g, nullptr, ysd, bc * m, pim, qs, st); }))) return rc;
-    if ((rc = staged(SKEI_STAGE_ADJ_SKETCH, st,
-                     [&] { return launch_radon_adj(g, qs, bc, angle_idx, m, z, r, st); })))
-        return rc;
-    if ((rc = staged(SKEI_STAGE_ADJ_MC, st,
-                     [&] { return launch_radon_adj(g, rmc, batch, mc_idx, m_mc, amc, nullptr, st); })))
-        return rc;
-    return staged(SKEI_STAGE_ROTATE_ADJ, st, [&] {
-        return launch_rotate_adj(z, batch, copies, g->n, cos_sin, 2.0f * lambda / copies, amc, -2.0f, grad, st);
-    });
+    return staged(SKEI_STAGE_ROTATE_ADJ, st, [&] { return rotate_adj_run(inline_jobs(&J.radj, 1), st); });
 }
 
 }  // extern "C"

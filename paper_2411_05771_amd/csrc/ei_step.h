@@ -1,0 +1,63 @@
+// The EI loss/gradient step as per-stage job lists, shared by the one-problem
+// entry point (skei_ei_loss_grad) and batched plans (skei_ei_plan_*): both
+// build every problem's jobs with ei_problem_jobs, so a problem computes the
+// same thing, bitwise, alone or batched.
+#pragma once
+
+#include "skei_internal.h"
+
+namespace skei {
+
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Device buffers of one problem's step, carved from a workspace.
+struct EiBuffers {
+    float *z, *zT, *r, *rT, *xT;   // [B*C][N][N] x4, [B][N][N]
+    double *ysd;                   // [B*C][m][N_det] doubles (its first half doubles as float ys)
+    float *ys, *qs;                // [B*C][m][N_det]
+    float *rmc;                    // [B][m_mc][N_det]
+    float *amc;                    // [B][N][N]
+    double *pmc, *pei;             // partial sums of squares
+    size_t n_pmc, n_pei;           // their capacities
+};
+
+size_t ei_workspace_bytes(const skei_geom *g, int batch, int m_mc, int m, int copies);
+// false when `bytes` is too small.
+bool ei_carve(const skei_geom *g, int batch, int m_mc, int m, int copies, void *work, size_t bytes, EiBuffers &b);
+
+// All jobs of one problem's step.  Two-job stages (ROTATE, FWD, ADJ) hold the
+// sketch/copies job first and the MC / plain-image job second.
+struct EiJobs {
+    RotJob rot[2];
+    RayJob fwd[2];
+    RayShape fwd_shape[2];
+    RampJob ramp;
+    GatherJob bp;
+    RedJob red;
+    RayJob bpt;
+    RayShape bpt_shape;
+    RampJob rampT;
+    GatherJob adj[2];
+    RotAdjJob radj;
+    bool grad;
+};
+
+// fwd_rpt / bpt_rpt: rays-per-thread caps of the ray jobs (0 = per-problem
+// automatic shape, honouring the geometry's tuning).
+int ei_problem_jobs(const skei_ei_problem &p, const EiBuffers &b, int fwd_rpt, int bpt_rpt, EiJobs &J);
+
+// Stage probe (skei_probe_set): events around the launch of one stage.
+int probe_begin(int stage, hipStream_t st);
+int probe_end(int stage, hipStream_t st);
+
+template <typename F>
+int staged(int stage, hipStream_t st, F &&fn)
+{
+    int rc = probe_begin(stage, st);
+    if (rc) return rc;
+    rc = fn();
+    if (rc) return rc;
+    return probe_end(stage, st);
+}
+
+}  // namespace skei

@@ -6,10 +6,12 @@
 // across steps: positions are always recomputed from indices with one FMA.
 #include <cmath>
 #include <cstdio>
+#include <mutex>
 #include <new>
 #include <vector>
 
 #include "skei_internal.h"
+#include "work.h"
 
 namespace skei {
 
@@ -17,6 +19,29 @@ int check_launch()
 {
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? SKEI_OK : SKEI_ELAUNCH;
+}
+
+int resident_workgroups(const void *kernel, int block, size_t shm)
+{
+    struct Entry {
+        const void *k;
+        int block, dev;
+        size_t shm;
+        int n;
+    };
+    static std::mutex mu;
+    static std::vector<Entry> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return -1;
+    std::lock_guard<std::mutex> lock(mu);
+    for (const Entry &e : cache)
+        if (e.k == kernel && e.block == block && e.shm == shm && e.dev == dev) return e.n;
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, shm) != hipSuccess) return -1;
+    const int n = cus * (per_cu < 1 ? 1 : per_cu);
+    cache.push_back(Entry{kernel, block, dev, shm, n});
+    return n;
 }
 
 }  // namespace skei

@@ -13,6 +13,7 @@
 #include <cmath>
 
 #include "skei_internal.h"
+#include "work.h"
 
 namespace skei {
 namespace {
@@ -30,53 +31,44 @@ struct GatherAngle {
     float w, wm1;      // Joseph width max(|cos|,|sin|) and w - 1
 };
 
-// XCD-major tile mapping (workgroup L runs on XCD L % 8): each XCD takes a
-// contiguous range of (image, tile) items, so an image's tiles share one L2.
-__device__ __forceinline__ bool decode_item(int total, int &item)
-{
-    const int L = blockIdx.x;
-    const int per = (total + 7) >> 3;
-    const int pos = L >> 3;
-    item = (L & 7) * per + pos;
-    return pos < per && item < total;
-}
+// A workgroup holds a 16 x 16 tile x GA angle groups.  The listed angles are
+// split into four fixed classes (r % 4); each class is summed in increasing
+// r, and the four class sums are added in a fixed order.  Thread (pixel, ga)
+// owns the classes ga, ga + GA, ...  Positions are relative to the fixed
+// 16 x 16 tile grid, so every pixel's arithmetic is the same whatever GA, the
+// batch size or the other jobs of the launch -- results are bitwise invariant.
+constexpr int kClasses = 4;
 
-// A workgroup holds a 16 x 16 tile x GA angle groups: thread (pixel, ga) sums
-// the listed angles r with r % GA == ga, and the GA partial sums are added in a
-// fixed order through LDS.  GA depends only on m, and positions are relative
-// to the fixed 16 x 16 tile grid, so every pixel's arithmetic is the same
-// whatever the batch size -- results are bitwise batch invariant.
-template <int KIND, int MODE, int GA>
-__global__ void __launch_bounds__(256 * GA) k_gather(const float *__restrict__ in, int n, int n_det,
-                                                     const int32_t *__restrict__ idx, int m,
-                                                     const AngleRow *__restrict__ tab, float scale,
-                                                     float *__restrict__ out, const float *__restrict__ other,
-                                                     double *__restrict__ partial, int total,
-                                                     float *__restrict__ outT)
+template <int KIND, int GA>
+__device__ __forceinline__ void gather_item(const GatherJob &J, long long item)
 {
-    constexpr int TILE = 16, NPIX = TILE * TILE, BS = NPIX * GA, WIN = 2 * TILE;
+    constexpr int TILE = 16, NPIX = TILE * TILE, BS = NPIX * GA, WIN = 2 * TILE, NC = kClasses / GA;
     __shared__ GatherAngle prm[kAngleChunk];
     __shared__ int kst[kAngleChunk];                  // first detector of each window
     __shared__ float iw2[kAngleChunk];                // 1/w^2 (Joseph weights)
     __shared__ float2 win[kAngleChunk * WIN];
-    __shared__ float part[GA][NPIX];
+    __shared__ float part[kClasses][NPIX];
     __shared__ float tileT[TILE][TILE + 1];
     __shared__ double red[NPIX / 64];
+    static_assert(kAngleChunk % kClasses == 0, "angle chunks must keep the classes aligned");
 
-    int item;
-    if (!decode_item(total, item)) return;
+    const int n = J.n, n_det = J.n_det, m = J.m;
+    const int32_t *__restrict__ idx = J.idx;
+    const AngleRow *__restrict__ tab = J.tab;
     const int tiles_x = (n + TILE - 1) / TILE;
     const int tiles = tiles_x * tiles_x;
-    const int b = item / tiles, tile = item - b * tiles;
+    const int b = (int)(item / tiles), tile = (int)(item - (long long)b * tiles);
     const int i0 = (tile / tiles_x) * TILE, j0 = (tile % tiles_x) * TILE;
     const int tid = threadIdx.x;
     const int px = tid % NPIX, ga = tid / NPIX;
     const int dx = px % TILE, dy = px / TILE;
     const double fdx = (double)dx, fdy = (double)dy;
     const double cN = 0.5 * (n - 1), cD = 0.5 * (n_det - 1);
-    const float *src = in + (size_t)b * m * n_det;
+    const float *src = J.in + (size_t)b * m * n_det;
 
-    float acc = 0.0f;
+    float acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; c++) acc[c] = 0.0f;
     for (int A0 = 0; A0 < m; A0 += kAngleChunk) {
         const int Ac = min(kAngleChunk, m - A0);
         __syncthreads();
@@ -104,33 +96,39 @@ __global__ void __launch_bounds__(256 * GA) k_gather(const float *__restrict__ i
                 win[e] = make_float2(v0, v1 - v0);
         }
         __syncthreads();
-#pragma unroll 4
-        for (int a = ga; a < Ac; a += GA) {
-            const GatherAngle p = prm[a];
-            // window-local detector coordinate in double: exact to ~1e-15 px,
-            // at the same issue rate as float on this device
-            const double tl = fma(fdx, p.c, fma(fdy, p.s, p.t0));
-            const int k0 = (int)tl;                          // 1 <= tl < WIN - 1 by construction
-            const float f = (float)__builtin_amdgcn_fract(tl);
-            const float2 e = win[a * WIN + k0];
-            if (KIND == kJosephAdj) {
-                // weights Lambda((k - t)/w)/w for k = k0, k0+1 (the 1/w^2 is in the window)
-                const float wa = fmaxf(p.w - f, 0.0f);
-                const float wb = fmaxf(f + p.wm1, 0.0f);
-                acc = fmaf(wa, e.x, acc);
-                acc = fmaf(wb, e.y, acc);
-            } else {
-                acc += e.x;
-                acc = fmaf(f, e.y, acc);
+        for (int a4 = 0; a4 < Ac; a4 += kClasses) {
+#pragma unroll
+            for (int c = 0; c < NC; c++) {
+                const int a = a4 + ga + c * GA;
+                if (a < Ac) {
+                    const GatherAngle p = prm[a];
+                    // window-local detector coordinate in double: exact to ~1e-15 px
+                    const double tl = fma(fdx, p.c, fma(fdy, p.s, p.t0));
+                    const int k0 = (int)tl;                          // 1 <= tl < WIN - 1 by construction
+                    const float f = (float)__builtin_amdgcn_fract(tl);
+                    const float2 e = win[a * WIN + k0];
+                    if (KIND == kJosephAdj) {
+                        // weights Lambda((k - t)/w)/w for k = k0, k0+1 (the 1/w^2 is in the window)
+                        const float wa = fmaxf(p.w - f, 0.0f);
+                        const float wb = fmaxf(f + p.wm1, 0.0f);
+                        acc[c] = fmaf(wa, e.x, acc[c]);
+                        acc[c] = fmaf(wb, e.y, acc[c]);
+                    } else {
+                        acc[c] += e.x;
+                        acc[c] = fmaf(f, e.y, acc[c]);
+                    }
+                }
             }
         }
     }
-    if (GA > 1) {
-        part[ga][px] = acc;
-        __syncthreads();
-        acc = part[0][px];
+    float sum;
+    if constexpr (GA == 1) {
+        sum = ((acc[0] + acc[1]) + acc[2]) + acc[3];
+    } else {
 #pragma unroll
-        for (int g = 1; g < GA; g++) acc += part[g][px];
+        for (int c = 0; c < NC; c++) part[ga + c * GA][px] = acc[c];
+        __syncthreads();
+        sum = ((part[0][px] + part[1][px]) + part[2][px]) + part[3][px];
     }
 
     // the threads of angle group 0 write the tile
@@ -139,60 +137,55 @@ __global__ void __launch_bounds__(256 * GA) k_gather(const float *__restrict__ i
     float v = 0.0f;
     if (ga == 0 && i < n && j < n) {
         const size_t o = ((size_t)b * n + i) * n + j;
-        v = acc * scale;
-        if (MODE == kResidSub) {
-            v = other[o] - v;
+        v = sum * J.scale;
+        if (J.other) {
+            v = J.other[o] - v;
             ss = (double)v * (double)v;
         }
-        out[o] = v;
+        J.out[o] = v;
     }
-    if (outT) {   // the tile again, transposed through LDS (coalesced stores)
+    if (J.outT) {   // the tile again, transposed through LDS (coalesced stores)
         if (ga == 0) tileT[dy][dx] = v;
         __syncthreads();
         const int it = j0 + dy, jt = i0 + dx;
-        if (ga == 0 && it < n && jt < n) outT[((size_t)b * n + it) * n + jt] = tileT[dx][dy];
+        if (ga == 0 && it < n && jt < n) J.outT[((size_t)b * n + it) * n + jt] = tileT[dx][dy];
     }
-    if (MODE == kResidSub && partial) {
+    if (J.other && J.partial) {
         ss = wave_sum(ss);
         if ((tid & 63) == 0 && tid < NPIX) red[tid >> 6] = ss;
         __syncthreads();
         if (tid == 0) {
             double s = 0.0;
             for (int w = 0; w < NPIX / 64; w++) s += red[w];
-            partial[item] = s;
+            J.partial[item] = s;
         }
     }
 }
 
-// Angle groups per pixel: a function of m only (never of the batch).
-int angle_groups(int m) { return m >= 256 ? 4 : m >= 64 ? 2 : 1; }
+template <int KIND, int GA>
+__global__ void __launch_bounds__(256 * GA) k_gather(const JobList<GatherJob> L)
+{
+    for_each_item(L, [&](const GatherJob &J, long long item) { gather_item<KIND, GA>(J, item); });
+}
 
 template <int KIND, int GA>
-int gather_launch_g(const skei_geom *g, const float *in, int batch, const int32_t *idx, int m, float scale,
-                    float *out, const float *other, double *partial, hipStream_t st, float *outT)
+int gather_launch(const JobList<GatherJob> &L, hipStream_t st)
 {
-    const int n = g->n;
-    const long long tiles = (long long)((n + 15) / 16) * ((n + 15) / 16);
-    const long long total = tiles * batch;
-    if (total > 0x0fffffffLL) return SKEI_ERANGE;
-    const dim3 grid((unsigned)(8 * ((total + 7) / 8))), block(256 * GA);
-    if (other)
-        hipLaunchKernelGGL((k_gather<KIND, kResidSub, GA>), grid, block, 0, st, in, n, g->n_det, idx, m, g->tab,
-                           scale, out, other, partial, (int)total, outT);
-    else
-        hipLaunchKernelGGL((k_gather<KIND, kPlain, GA>), grid, block, 0, st, in, n, g->n_det, idx, m, g->tab,
-                           scale, out, nullptr, nullptr, (int)total, outT);
+    if (L.total <= 0) return SKEI_OK;
+    const long long grid = launch_grid(L, reinterpret_cast<const void *>(&k_gather<KIND, GA>), 256 * GA, 0);
+    if (grid <= 0 || grid > 0x7fffffffLL) return SKEI_ERANGE;
+    hipLaunchKernelGGL((k_gather<KIND, GA>), dim3((unsigned)grid), dim3(256 * GA), 0, st, L);
     return check_launch();
 }
 
 template <int KIND>
-int gather_launch(const skei_geom *g, const float *in, int batch, const int32_t *idx, int m, float scale,
-                  float *out, const float *other, double *partial, hipStream_t st, float *outT = nullptr)
+int gather_launch_ga(int ga, const JobList<GatherJob> &L, hipStream_t st)
 {
-    switch (angle_groups(m)) {
-    case 4: return gather_launch_g<KIND, 4>(g, in, batch, idx, m, scale, out, other, partial, st, outT);
-    case 2: return gather_launch_g<KIND, 2>(g, in, batch, idx, m, scale, out, other, partial, st, outT);
-    default: return gather_launch_g<KIND, 1>(g, in, batch, idx, m, scale, out, other, partial, st, outT);
+    switch (ga) {
+    case 1: return gather_launch<KIND, 1>(L, st);
+    case 2: return gather_launch<KIND, 2>(L, st);
+    case 4: return gather_launch<KIND, 4>(L, st);
+    default: return SKEI_ERANGE;
     }
 }
 
@@ -202,22 +195,44 @@ static_assert(2 * 16 >= 2 + 22 + 2, "detector window too small for the pixel til
 
 }  // namespace
 
-size_t gather_partials(const skei_geom *g, int batch)
+int gather_groups_auto(int m) { return m >= 256 ? 2 : 1; }
+
+size_t gather_items(int n, int batch)
 {
-    const size_t t = (size_t)((g->n + 15) / 16);
+    const size_t t = (size_t)((n + 15) / 16);
     return t * t * batch;
 }
 
-int launch_radon_adj(const skei_geom *g, const float *y, int batch, const int32_t *idx, int m, float *x,
-                     const float *other, hipStream_t st)
+GatherJob make_gather_job(const skei_geom *g, const float *in, int batch, const int32_t *idx, int m, float scale,
+                          float *out, const float *other, double *partial, float *outT)
 {
-    return gather_launch<kJosephAdj>(g, y, batch, idx, m, 1.0f, x, other, nullptr, st);
+    GatherJob J{};
+    J.in = in;
+    J.idx = idx;
+    J.tab = g->tab;
+    J.out = out;
+    J.other = other;
+    J.partial = partial;
+    J.outT = outT;
+    J.n = g->n;
+    J.n_det = g->n_det;
+    J.m = m;
+    J.scale = scale;
+    J.items = (long long)gather_items(g->n, batch);
+    return J;
 }
 
-int launch_backproject(const skei_geom *g, const float *q, int batch, const int32_t *idx, int m, float scale,
-                       float *x, const float *other, double *partial, hipStream_t st, float *xT)
+int gather_run(int kind, int ga, const JobList<GatherJob> &L, hipStream_t st)
 {
-    return gather_launch<kBackproject>(g, q, batch, idx, m, scale, x, other, partial, st, xT);
+    return kind == kGatherJosephAdj ? gather_launch_ga<kJosephAdj>(ga, L, st)
+                                    : gather_launch_ga<kBackproject>(ga, L, st);
+}
+
+int launch_gather(int kind, const skei_geom *g, const float *in, int batch, const int32_t *idx, int m, float scale,
+                  float *out, const float *other, double *partial, float *outT, hipStream_t st)
+{
+    const GatherJob J = make_gather_job(g, in, batch, idx, m, scale, out, other, partial, outT);
+    return gather_run(kind, gather_groups_auto(m), inline_jobs(&J, 1), st);
 }
 
 }  // namespace skei

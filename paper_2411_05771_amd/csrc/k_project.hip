@@ -29,6 +29,7 @@
 #include <algorithm>
 
 #include "skei_internal.h"
+#include "work.h"
 
 namespace skei {
 namespace {
@@ -45,57 +46,74 @@ constexpr float kTwoM32 = 2.3283064365386963e-10f;   // 2^-32
 
 enum Kind : int { kFwd = 0, kBpT = 1 };
 
-struct Plan {
-    int G, nseg, seg, rpt, R, pitch, ngroups;
-    long long total;
-    size_t shm;
-};
-
 // LDS line pitch in floats: kLinePad zero entries on each side, 16-byte multiple.
 int line_pitch(int n) { return ((n + 2 * kLinePad) + 3) & ~3; }
 
-int make_plan(const skei_geom *g, int batch, int m, const RayTune &t, Plan &p)
+}  // namespace
+
+int make_ray_job(const skei_geom *g, const float *x, const float *xT, int batch, const int32_t *idx, int m, void *y,
+                 const float *yfull, double *partial, const RayTune &t, int rpt_cap, RayJob &J, RayShape &shape)
 {
     const int n = g->n, nd = g->n_det;
     const long long base_items = (long long)batch * m;
-    int G = t.group > 0 ? t.group : (base_items >= 2048 ? 4 : base_items >= 1024 ? 2 : 1);
-    G = std::max(1, std::min(std::min(G, kMaxG), m));
-    int nseg = t.split > 0 ? t.split : ((base_items < 512 && nd >= 128) ? 2 : 1);
+    const int cap = rpt_cap > 0 ? std::min(rpt_cap, kRaysMax / kBlock) * kBlock : kRaysMax;
+    int nseg = t.split > 0 ? t.split
+                           : rpt_cap > 0 ? (nd + cap - 1) / cap
+                                         : ((base_items < 512 && nd >= 128) ? 2 : 1);
     nseg = std::max(1, std::min(nseg, nd));
+    int G;
+    if (t.group > 0)
+        G = t.group;
+    else if (rpt_cap > 0)
+        G = std::max(1, cap / ((nd + nseg - 1) / nseg));
+    else
+        G = base_items >= 2048 ? 4 : base_items >= 1024 ? 2 : 1;
+    G = std::max(1, std::min(std::min(G, kMaxG), m));
     for (;;) {
         const int seg = (nd + nseg - 1) / nseg;
-        if ((long long)G * seg <= kRaysMax) break;
+        if ((long long)G * seg <= cap) break;
         if (G > 1)
             G--;
         else
             nseg++;
     }
-    p.G = G;
-    p.nseg = nseg;
-    p.seg = (nd + nseg - 1) / nseg;
-    p.rpt = (G * p.seg + kBlock - 1) / kBlock;
-    p.pitch = line_pitch(n);
-    const int r_lds = (int)(kLdsBudget / (2 * (size_t)p.pitch * sizeof(float)));
+    J = RayJob{};
+    J.x = x;
+    J.xT = xT;
+    J.idx = idx;
+    J.tab = g->tab;
+    J.y = y;
+    J.yfull = yfull;
+    J.partial = partial;
+    J.n = n;
+    J.n_det = nd;
+    J.m = m;
+    J.n_angles = g->n_angles;
+    J.G = G;
+    J.nseg = nseg;
+    J.seg = (nd + nseg - 1) / nseg;
+    J.ngroups = (m + G - 1) / G;
+    J.pitch = line_pitch(n);
+    const int r_lds = (int)(kLdsBudget / (2 * (size_t)J.pitch * sizeof(float)));
     int R = std::min(std::max(r_lds, 1), std::min(64, n));
     if (t.lines > 0) R = std::min(R, t.lines);
-    p.R = R;
-    p.shm = 2 * (size_t)R * p.pitch * sizeof(float);
-    if (p.shm > 64 * 1024) return SKEI_ERANGE;
-    p.ngroups = (m + G - 1) / G;
-    p.total = (long long)batch * p.ngroups * p.nseg;
+    J.R = R;
+    J.resid = yfull != nullptr;
+    J.items = (long long)batch * J.ngroups * J.nseg;
+    shape.rpt = (G * J.seg + kBlock - 1) / kBlock;
+    shape.shm = 2 * (size_t)R * J.pitch * sizeof(float);
+    if (shape.shm > 64 * 1024 || shape.rpt > kRaysMax / kBlock) return SKEI_ERANGE;
     return SKEI_OK;
 }
 
-// XCD-major work mapping: workgroup L runs on XCD L % 8; work items are split
-// into 8 contiguous ranges, one per XCD.  Returns false for padding groups.
-__device__ __forceinline__ bool decode_item(long long total, long long &item)
+size_t ray_items_max(const skei_geom *g, int batch, int m, const RayTune &t)
 {
-    const long long L = blockIdx.x;
-    const long long per = (total + 7) >> 3;
-    const long long pos = L >> 3;
-    item = (L & 7) * per + pos;
-    return pos < per && item < total;
+    // G >= 1 and at most max(2, ceil(N_det / 256), split) segments per angle
+    const int nseg = std::max(std::max(2, (g->n_det + kBlock - 1) / kBlock), t.split);
+    return (size_t)batch * m * nseg;
 }
+
+namespace {
 
 __device__ __forceinline__ int wave_min(int v)
 {
@@ -199,30 +217,31 @@ __device__ __forceinline__ void dma_wait() { __builtin_amdgcn_s_waitcnt(0); }
 
 // ---------------------------------------------------------------------------
 // KIND kFwd: y[b][r][k] = (1/w) sum_M lerp(line_M, u(k, M))       (Joseph A_S)
-//   MODE kResidSub: y = yfull[b][idx[r]][k] - that, in double; partial[] = sum y^2.
+//   resid jobs: y = yfull[b][idx[r]][k] - that, in double; partial[item] = sum y^2.
 // KIND kBpT: q[b][r][k] = sum_M sum_j Lambda(w (j - u(k, M))) line_M[j]    (B_S^T)
 //   The pixels within unit distance of the ray in s are the (at most three)
 //   entries within 1/w of u; the four candidates j0-1 .. j0+2 cover them.
 // ---------------------------------------------------------------------------
-template <int KIND, int RPT, int MODE, typename OUT>
-__global__ void __launch_bounds__(kBlock) k_ray(const float *__restrict__ x, const float *__restrict__ xT, int n,
-                                                int n_det,
-                                                const int32_t *__restrict__ idx, int m,
-                                                const AngleRow *__restrict__ tab, int G, int nseg, int seg,
-                                                int ngroups, long long total, int R, int pitch,
-                                                OUT *__restrict__ y, const float *__restrict__ yfull, int n_angles,
-                                                double *__restrict__ partial)
+template <int KIND, int RPT, typename OUT>
+__device__ __forceinline__ void ray_item(const RayJob &J, long long item, float *lds)
 {
     // Lowest tap entry read: j0 for the forward walk, j0 - 1 for B^T; taps
     // below -kLinePad (and above n + 1) are clamped onto the zero borders.
     constexpr int kBias = KIND == kFwd ? kLinePad : kLinePad - 1;
-    extern __shared__ __align__(16) float lds[];
     __shared__ AngleRow ang[kMaxG];
     __shared__ int wrange[2][kWaves];
     __shared__ double red[kWaves];
 
-    long long item;
-    if (!decode_item(total, item)) return;
+    const float *__restrict__ x = J.x;
+    const float *__restrict__ xT = J.xT;
+    const int32_t *__restrict__ idx = J.idx;
+    const AngleRow *__restrict__ tab = J.tab;
+    OUT *__restrict__ y = static_cast<OUT *>(J.y);
+    const float *__restrict__ yfull = J.yfull;
+    double *__restrict__ partial = J.partial;
+    const int n = J.n, n_det = J.n_det, m = J.m, n_angles = J.n_angles;
+    const int G = J.G, nseg = J.nseg, seg = J.seg, ngroups = J.ngroups, R = J.R, pitch = J.pitch;
+    const bool resid = KIND == kFwd && J.resid;
     const int per_img = ngroups * nseg;
     const int b = (int)(item / per_img);
     const int rem = (int)(item - (long long)b * per_img);
@@ -407,7 +426,7 @@ __global__ void __launch_bounds__(kBlock) k_ray(const float *__restrict__ x, con
         const size_t o = ((size_t)b * m + r0 + rg[q]) * n_det + rk[q];
         if constexpr (KIND == kFwd) {
             double v = accd[q] * A.scale;
-            if (MODE == kResidSub) {
+            if (resid) {
                 const int a = idx[r0 + rg[q]];
                 v = (double)yfull[((size_t)b * n_angles + a) * n_det + rk[q]] - v;
                 const float vf = (float)v;
@@ -420,7 +439,7 @@ __global__ void __launch_bounds__(kBlock) k_ray(const float *__restrict__ x, con
             y[o] = (OUT)accd[q];
         }
     }
-    if (MODE == kResidSub) {
+    if (resid) {
         ss = wave_sum(ss);
         if ((tid & 63) == 0) red[tid >> 6] = ss;
         __syncthreads();
@@ -432,19 +451,40 @@ __global__ void __launch_bounds__(kBlock) k_ray(const float *__restrict__ x, con
     }
 }
 
-template <int KIND, int MODE, typename OUT>
-int ray_launch(const Plan &p, hipStream_t st, const float *x, const float *xT, int n, int n_det, const int32_t *idx,
-               int m, const AngleRow *tab, OUT *y, const float *yfull, int n_angles, double *partial)
+template <int KIND, int RPT, typename OUT>
+__global__ void __launch_bounds__(kBlock) k_ray(const JobList<RayJob> L)
 {
-    const long long per = (p.total + 7) / 8;
-    if (8 * per > 0x7fffffffLL) return SKEI_ERANGE;
-    const dim3 grid((unsigned)(8 * per)), block(kBlock);
-#define SKEI_RAY_CASE(P)                                                                                       \
-    case P:                                                                                                    \
-        hipLaunchKernelGGL((k_ray<KIND, P, MODE, OUT>), grid, block, p.shm, st, x, xT, n, n_det, idx, m, tab, p.G, \
-                           p.nseg, p.seg, p.ngroups, p.total, p.R, p.pitch, y, yfull, n_angles, partial);      \
-        break;
-    switch (p.rpt) {
+    extern __shared__ __align__(16) float lds[];
+    for_each_item(L, [&](const RayJob &J, long long item) { ray_item<KIND, RPT, OUT>(J, item, lds); });
+}
+
+template <int KIND, typename OUT>
+const void *ray_kernel(int rpt)
+{
+    switch (rpt) {
+    case 1: return reinterpret_cast<const void *>(&k_ray<KIND, 1, OUT>);
+    case 2: return reinterpret_cast<const void *>(&k_ray<KIND, 2, OUT>);
+    case 3: return reinterpret_cast<const void *>(&k_ray<KIND, 3, OUT>);
+    case 4: return reinterpret_cast<const void *>(&k_ray<KIND, 4, OUT>);
+    case 5: return reinterpret_cast<const void *>(&k_ray<KIND, 5, OUT>);
+    case 6: return reinterpret_cast<const void *>(&k_ray<KIND, 6, OUT>);
+    case 7: return reinterpret_cast<const void *>(&k_ray<KIND, 7, OUT>);
+    case 8: return reinterpret_cast<const void *>(&k_ray<KIND, 8, OUT>);
+    default: return nullptr;
+    }
+}
+
+template <int KIND, typename OUT>
+int ray_launch(int rpt, size_t shm, const JobList<RayJob> &L, hipStream_t st)
+{
+    const void *kern = ray_kernel<KIND, OUT>(rpt);
+    if (!kern) return SKEI_ERANGE;
+    if (L.total <= 0) return SKEI_OK;
+    const long long grid = launch_grid(L, kern, kBlock, shm);
+    if (grid <= 0 || grid > 0x7fffffffLL) return SKEI_ERANGE;
+    switch (rpt) {
+#define SKEI_RAY_CASE(P)                                                                                 \
+    case P: hipLaunchKernelGGL((k_ray<KIND, P, OUT>), dim3((unsigned)grid), dim3(kBlock), shm, st, L); break;
         SKEI_RAY_CASE(1)
         SKEI_RAY_CASE(2)
         SKEI_RAY_CASE(3)
@@ -453,45 +493,38 @@ int ray_launch(const Plan &p, hipStream_t st, const float *x, const float *xT, i
         SKEI_RAY_CASE(6)
         SKEI_RAY_CASE(7)
         SKEI_RAY_CASE(8)
-    default: return SKEI_ERANGE;
-    }
 #undef SKEI_RAY_CASE
+    }
     return check_launch();
 }
 
 }  // namespace
 
-size_t radon_fwd_partials(const skei_geom *g, int batch, int m, const RayTune &tune)
+int ray_run(int kind, bool out_double, int rpt, size_t shm, const JobList<RayJob> &L, hipStream_t st)
 {
-    Plan p;
-    if (make_plan(g, batch, m, tune, p) != SKEI_OK) return 0;
-    return (size_t)p.total;
+    if (shm > 64 * 1024) return SKEI_ERANGE;
+    if (kind == kRayFwd) return out_double ? SKEI_EINVAL : ray_launch<kFwd, float>(rpt, shm, L, st);
+    return out_double ? ray_launch<kBpT, double>(rpt, shm, L, st) : ray_launch<kBpT, float>(rpt, shm, L, st);
 }
 
 int launch_radon_fwd(const skei_geom *g, const float *x, const float *xT, int batch, const int32_t *idx, int m,
                      float *y, const float *yfull, double *partial, const RayTune &tune, hipStream_t st)
 {
-    Plan p;
-    int rc = make_plan(g, batch, m, tune, p);
+    RayJob J;
+    RayShape sh;
+    int rc = make_ray_job(g, x, xT, batch, idx, m, y, yfull, partial, tune, 0, J, sh);
     if (rc) return rc;
-    if (yfull)
-        return ray_launch<kFwd, kResidSub, float>(p, st, x, xT, g->n, g->n_det, idx, m, g->tab, y, yfull,
-                                                  g->n_angles, partial);
-    return ray_launch<kFwd, kPlain, float>(p, st, x, xT, g->n, g->n_det, idx, m, g->tab, y, nullptr, g->n_angles,
-                                           nullptr);
+    return ray_run(kRayFwd, false, sh.rpt, sh.shm, inline_jobs(&J, 1), st);
 }
 
 int launch_bp_T(const skei_geom *g, const float *x, const float *xT, int batch, const int32_t *idx, int m, float *qf,
                 double *qd, const RayTune &tune, hipStream_t st)
 {
-    Plan p;
-    int rc = make_plan(g, batch, m, tune, p);
+    RayJob J;
+    RayShape sh;
+    int rc = make_ray_job(g, x, xT, batch, idx, m, qd ? (void *)qd : (void *)qf, nullptr, nullptr, tune, 0, J, sh);
     if (rc) return rc;
-    if (qd)
-        return ray_launch<kBpT, kPlain, double>(p, st, x, xT, g->n, g->n_det, idx, m, g->tab, qd, nullptr,
-                                                g->n_angles, nullptr);
-    return ray_launch<kBpT, kPlain, float>(p, st, x, xT, g->n, g->n_det, idx, m, g->tab, qf, nullptr, g->n_angles,
-                                           nullptr);
+    return ray_run(kRayBpT, qd != nullptr, sh.rpt, sh.shm, inline_jobs(&J, 1), st);
 }
 
 }  // namespace skei

@@ -3,6 +3,7 @@
 // then adds the partials in a fixed order.  Results do not depend on timing or
 // on what else runs on the device.
 #include "skei_internal.h"
+#include "work.h"
 
 namespace skei {
 namespace {
@@ -37,19 +38,23 @@ __global__ void __launch_bounds__(kRedBlock) k_sumsq(const float *__restrict__ a
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-__global__ void __launch_bounds__(kRedBlock) k_reduce2(const double *__restrict__ p0, size_t n0, double w0,
-                                                       const double *__restrict__ p1, size_t n1, double w1,
-                                                       double *__restrict__ out)
+__device__ __forceinline__ void reduce_item(const RedJob &J)
 {
     __shared__ double sh[kRedBlock / 64];
     double a0 = 0.0, a1 = 0.0;
-    for (size_t i = threadIdx.x; i < n0; i += kRedBlock) a0 += p0[i];
-    if (p1)
-        for (size_t i = threadIdx.x; i < n1; i += kRedBlock) a1 += p1[i];
+    for (long long i = threadIdx.x; i < J.n0; i += kRedBlock) a0 += J.p0[i];
+    if (J.p1)
+        for (long long i = threadIdx.x; i < J.n1; i += kRedBlock) a1 += J.p1[i];
+    __syncthreads();   // an earlier item of this workgroup may still read sh[]
     const double s0 = block_sum(a0, sh);
     __syncthreads();
     const double s1 = block_sum(a1, sh);
-    if (threadIdx.x == 0) out[0] = w0 * s0 + (p1 ? w1 * s1 : 0.0);
+    if (threadIdx.x == 0) J.out[0] = J.w0 * s0 + (J.p1 ? J.w1 * s1 : 0.0);
+}
+
+__global__ void __launch_bounds__(kRedBlock) k_reduce2(const JobList<RedJob> L)
+{
+    for_each_item(L, [&](const RedJob &J, long long) { reduce_item(J); });
 }
 
 }  // namespace
@@ -64,11 +69,28 @@ int launch_sumsq(const float *a, const float *b, size_t len, double *partial, hi
     return check_launch();
 }
 
+int reduce_run(const JobList<RedJob> &L, hipStream_t st)
+{
+    if (L.total <= 0) return SKEI_OK;
+    const long long grid = launch_grid(L, reinterpret_cast<const void *>(&k_reduce2), kRedBlock, 0);
+    if (grid <= 0 || grid > 0x7fffffffLL) return SKEI_ERANGE;
+    hipLaunchKernelGGL(k_reduce2, dim3((unsigned)grid), dim3(kRedBlock), 0, st, L);
+    return check_launch();
+}
+
 int launch_reduce2(const double *p0, size_t n0, double w0, const double *p1, size_t n1, double w1, double *out,
                    hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(kRedBlock), 0, st, p0, n0, w0, p1, n1, w1, out);
-    return check_launch();
+    RedJob J{};
+    J.p0 = p0;
+    J.p1 = p1;
+    J.out = out;
+    J.n0 = (long long)n0;
+    J.n1 = (long long)n1;
+    J.w0 = w0;
+    J.w1 = w1;
+    J.items = 1;
+    return reduce_run(inline_jobs(&J, 1), st);
 }
 
 }  // namespace skei

@@ -12,6 +12,7 @@
 #include <cmath>
 
 #include "skei_internal.h"
+#include "work.h"
 
 namespace skei {
 namespace {
@@ -39,72 +40,71 @@ __device__ __forceinline__ Sample sample_point(int i, int j, float c, float s, d
     return r;
 }
 
-// One 16 x 16 output tile per workgroup; the tile is also written transposed
-// (through LDS, so both stores are coalesced) when outT is given.
-__global__ void __launch_bounds__(256) k_rotate(const float *__restrict__ x, int n, int copies,
-                                                const float *__restrict__ cs, float *__restrict__ out,
-                                                float *__restrict__ outT)
+// One 16 x 16 output tile per work item; the tile is also written transposed
+// (through LDS, so both stores are coalesced) when outT is given.  Jobs
+// without rotations (cs == nullptr) copy / transpose the image exactly.
+__device__ __forceinline__ void rotate_item(const RotJob &J, long long item)
 {
     __shared__ float tile[16][17];
+    const int n = J.n, copies = J.copies;
     const int tiles_x = (n + 15) / 16;
-    const int i0 = (blockIdx.x / tiles_x) * 16, j0 = (blockIdx.x % tiles_x) * 16;
-    const int bc = blockIdx.y;                 // b * copies + c
-    const int b = bc / copies, c = bc - b * copies;
+    const int tiles = tiles_x * tiles_x;
+    const long long bc = item / tiles;          // b * copies + c
+    const int t = (int)(item - bc * tiles);
+    const int i0 = (t / tiles_x) * 16, j0 = (t % tiles_x) * 16;
+    const long long b = bc / copies;
+    const int c = (int)(bc - b * copies);
     const int dx = threadIdx.x & 15, dy = threadIdx.x >> 4;
     const int i = i0 + dy, j = j0 + dx;
-    const double cN = 0.5 * (double)(n - 1);
+    const float *img = J.x + (size_t)b * n * n;
     float acc = 0.0f;
     if (i < n && j < n) {
-        const Sample sp = sample_point(i, j, cs[2 * c], cs[2 * c + 1], cN);
-        const float *img = x + (size_t)b * n * n;
+        if (J.cs) {
+            const double cN = 0.5 * (double)(n - 1);
+            const Sample sp = sample_point(i, j, J.cs[2 * c], J.cs[2 * c + 1], cN);
 #pragma unroll
-        for (int di = 0; di < 2; di++) {
-            const int ii = sp.i0 + di;
-            const float wv = di ? sp.av : 1.0f - sp.av;
+            for (int di = 0; di < 2; di++) {
+                const int ii = sp.i0 + di;
+                const float wv = di ? sp.av : 1.0f - sp.av;
 #pragma unroll
-            for (int dj = 0; dj < 2; dj++) {
-                const int jj = sp.j0 + dj;
-                const float wu = dj ? sp.au : 1.0f - sp.au;
-                if (ii >= 0 && ii < n && jj >= 0 && jj < n) acc = fmaf(wv * wu, img[(size_t)ii * n + jj], acc);
+                for (int dj = 0; dj < 2; dj++) {
+                    const int jj = sp.j0 + dj;
+                    const float wu = dj ? sp.au : 1.0f - sp.au;
+                    if (ii >= 0 && ii < n && jj >= 0 && jj < n) acc = fmaf(wv * wu, img[(size_t)ii * n + jj], acc);
+                }
             }
+        } else {
+            acc = img[(size_t)i * n + j];
         }
-        out[(size_t)bc * n * n + (size_t)i * n + j] = acc;
+        if (J.out) J.out[(size_t)bc * n * n + (size_t)i * n + j] = acc;
     }
-    if (outT) {
+    if (J.outT) {
+        __syncthreads();   // an earlier item of this workgroup may still read the tile
         tile[dy][dx] = acc;
         __syncthreads();
         const int it = j0 + dy, jt = i0 + dx;   // transposed position: row = original column
-        if (it < n && jt < n) outT[(size_t)bc * n * n + (size_t)it * n + jt] = tile[dx][dy];
+        if (it < n && jt < n) J.outT[(size_t)bc * n * n + (size_t)it * n + jt] = tile[dx][dy];
     }
 }
 
-// xT[b][j][i] = x[b][i][j], 16 x 16 tiles through LDS.
-__global__ void __launch_bounds__(256) k_transpose(const float *__restrict__ x, int n, float *__restrict__ xT)
+__global__ void __launch_bounds__(256) k_rotate(const JobList<RotJob> L)
 {
-    __shared__ float tile[16][17];
-    const int tiles_x = (n + 15) / 16;
-    const int i0 = (blockIdx.x / tiles_x) * 16, j0 = (blockIdx.x % tiles_x) * 16;
-    const size_t off = (size_t)blockIdx.y * n * n;
-    const int dx = threadIdx.x & 15, dy = threadIdx.x >> 4;
-    if (i0 + dy < n && j0 + dx < n) tile[dy][dx] = x[off + (size_t)(i0 + dy) * n + j0 + dx];
-    __syncthreads();
-    if (j0 + dy < n && i0 + dx < n) xT[off + (size_t)(j0 + dy) * n + i0 + dx] = tile[dx][dy];
+    for_each_item(L, [&](const RotJob &J, long long item) { rotate_item(J, item); });
 }
 
 // g[b][p'] = alpha * sum_c sum_p T_c[p][p'] h[b][c][p] + beta * add[b][p']
-// A workgroup covers 64 consecutive pixels x 4 copy groups (copies c = grp,
+// A work item covers 64 consecutive pixels x 4 copy groups (copies c = grp,
 // grp+4, ...); the four partial sums are added in a fixed order through LDS.
 constexpr int kRotPix = 64, kRotGroups = 4;
 
-__global__ void __launch_bounds__(256) k_rotate_adj(const float *__restrict__ h, int n, int copies,
-                                                    const float *__restrict__ cs, float alpha,
-                                                    const float *__restrict__ add, float beta,
-                                                    float *__restrict__ g)
+__device__ __forceinline__ void rotate_adj_item(const RotAdjJob &J, long long item)
 {
     __shared__ float part[kRotGroups][kRotPix];
+    const int n = J.n, copies = J.copies;
+    const long long blocks = ((long long)n * n + kRotPix - 1) / kRotPix;
+    const long long b = item / blocks;
     const int px = threadIdx.x & (kRotPix - 1), grp = threadIdx.x / kRotPix;
-    const int p = blockIdx.x * kRotPix + px;
-    const int b = blockIdx.y;
+    const int p = (int)(item - b * blocks) * kRotPix + px;
     const bool in = p < n * n;
     float acc = 0.0f;
     if (in) {
@@ -112,8 +112,8 @@ __global__ void __launch_bounds__(256) k_rotate_adj(const float *__restrict__ h,
         const double cN = 0.5 * (double)(n - 1);
         const double Xp = (double)jp - cN, Yp = (double)ip - cN;
         for (int c = grp; c < copies; c += kRotGroups) {
-            const float co = cs[2 * c], si = cs[2 * c + 1];
-            const float *hc = h + ((size_t)b * copies + c) * n * n;
+            const float co = J.cs[2 * c], si = J.cs[2 * c + 1];
+            const float *hc = J.h + ((size_t)b * copies + c) * n * n;
             // centre of the candidate set: the output position whose sample is p'
             const double colc = fma((double)co, Xp, fma(-(double)si, Yp, cN));
             const double rowc = fma((double)si, Xp, fma((double)co, Yp, cN));
@@ -137,41 +137,84 @@ __global__ void __launch_bounds__(256) k_rotate_adj(const float *__restrict__ h,
             }
         }
     }
+    __syncthreads();   // an earlier item of this workgroup may still read part[]
     part[grp][px] = acc;
     __syncthreads();
     if (grp == 0 && in) {
         const float s = ((part[0][px] + part[1][px]) + part[2][px]) + part[3][px];
-        float v = alpha * s;
-        if (add) v = fmaf(beta, add[(size_t)b * n * n + p], v);
-        g[(size_t)b * n * n + p] = v;
+        float v = J.alpha * s;
+        if (J.add) v = fmaf(J.beta, J.add[(size_t)b * n * n + p], v);
+        J.g[(size_t)b * n * n + p] = v;
     }
+}
+
+__global__ void __launch_bounds__(256) k_rotate_adj(const JobList<RotAdjJob> L)
+{
+    for_each_item(L, [&](const RotAdjJob &J, long long item) { rotate_adj_item(J, item); });
 }
 
 }  // namespace
 
-int launch_rotate(const float *x, int batch, int copies, int n, const float *cs, float *out, hipStream_t st,
-                  float *outT)
+RotJob make_rot_job(const float *x, int batch, int copies, int n, const float *cs, float *out, float *outT)
 {
-    const int t = (n + 15) / 16;
-    const dim3 grid(t * t, batch * copies);
-    hipLaunchKernelGGL(k_rotate, grid, dim3(256), 0, st, x, n, copies, cs, out, outT);
+    RotJob J{};
+    J.x = x;
+    J.cs = cs;
+    J.out = out;
+    J.outT = outT;
+    J.n = n;
+    J.copies = cs ? copies : 1;
+    const long long t = (n + 15) / 16;
+    J.items = t * t * batch * J.copies;
+    return J;
+}
+
+RotAdjJob make_rot_adj_job(const float *h, int batch, int copies, int n, const float *cs, float alpha,
+                           const float *add, float beta, float *g)
+{
+    RotAdjJob J{};
+    J.h = h;
+    J.cs = cs;
+    J.add = add;
+    J.g = g;
+    J.n = n;
+    J.copies = copies;
+    J.alpha = alpha;
+    J.beta = beta;
+    J.items = (((long long)n * n + kRotPix - 1) / kRotPix) * batch;
+    return J;
+}
+
+int rotate_run(const JobList<RotJob> &L, hipStream_t st)
+{
+    if (L.total <= 0) return SKEI_OK;
+    const long long grid = launch_grid(L, reinterpret_cast<const void *>(&k_rotate), 256, 0);
+    if (grid <= 0 || grid > 0x7fffffffLL) return SKEI_ERANGE;
+    hipLaunchKernelGGL(k_rotate, dim3((unsigned)grid), dim3(256), 0, st, L);
     return check_launch();
 }
 
-int launch_transpose(const float *x, int batch, int n, float *xT, hipStream_t st)
+int rotate_adj_run(const JobList<RotAdjJob> &L, hipStream_t st)
 {
-    const int t = (n + 15) / 16;
-    const dim3 grid(t * t, batch);
-    hipLaunchKernelGGL(k_transpose, grid, dim3(256), 0, st, x, n, xT);
+    if (L.total <= 0) return SKEI_OK;
+    const long long grid = launch_grid(L, reinterpret_cast<const void *>(&k_rotate_adj), 256, 0);
+    if (grid <= 0 || grid > 0x7fffffffLL) return SKEI_ERANGE;
+    hipLaunchKernelGGL(k_rotate_adj, dim3((unsigned)grid), dim3(256), 0, st, L);
     return check_launch();
+}
+
+int launch_rotate(const float *x, int batch, int copies, int n, const float *cs, float *out, float *outT,
+                  hipStream_t st)
+{
+    const RotJob J = make_rot_job(x, batch, copies, n, cs, out, outT);
+    return rotate_run(inline_jobs(&J, 1), st);
 }
 
 int launch_rotate_adj(const float *h, int batch, int copies, int n, const float *cs, float alpha,
                       const float *add, float beta, float *g, hipStream_t st)
 {
-    const dim3 grid((n * n + kRotPix - 1) / kRotPix, batch);
-    hipLaunchKernelGGL(k_rotate_adj, grid, dim3(256), 0, st, h, n, copies, cs, alpha, add, beta, g);
-    return check_launch();
+    const RotAdjJob J = make_rot_adj_job(h, batch, copies, n, cs, alpha, add, beta, g);
+    return rotate_adj_run(inline_jobs(&J, 1), st);
 }
 
 }  // namespace skei

@@ -1,0 +1,507 @@
+// Batched EI plans (skei_ei_plan_*): the EI step of many problems of
+// different sizes, one launch per stage for all of them, and the autotuner
+// that picks each stage's dispatch mode and launch shape.
+//
+// Every problem's jobs come from ei_problem_jobs, exactly as for the
+// one-problem entry point.  A stage's jobs are concatenated problem by
+// problem into one work list; the list is cut into kXcds contiguous ranges of
+// about equal estimated cost, one per XCD, so the items of one image stay on
+// one L2.  Persistent dispatch launches one resident wave of workgroups that
+// drain their XCD's range through an atomic cursor and then steal from the
+// other ranges; static dispatch launches one workgroup per item.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "ei_step.h"
+#include "skei_internal.h"
+
+using namespace skei;
+
+namespace {
+
+constexpr int kStages = SKEI_STAGE_COUNT;
+constexpr int kDefaultRpt = 3;
+
+struct StageCfg {
+    int dispatch = SKEI_DISPATCH_PERSISTENT;
+    int shape = 0;
+};
+
+struct StageTable {
+    int njobs = 0;
+    long long total = 0;
+    long long grid_static = 0;
+    int chunk = 1;     // persistent draws
+    size_t off_jobs = 0, off_first = 0, off_xr = 0;
+    // launch parameters
+    int rpt = 0;       // ray stages
+    size_t shm = 0;    // ray / ramp stages
+    int ga = 0;        // gather stages
+    int ramp_rpt = 0, ramp_block = 0;
+};
+
+bool is_ray_stage(int s) { return s == SKEI_STAGE_FWD || s == SKEI_STAGE_BP_T; }
+bool is_gather_stage(int s) { return s == SKEI_STAGE_BP_RESID || s == SKEI_STAGE_ADJ; }
+
+// Estimated cost of one item of a job (arbitrary units, only ratios matter).
+double item_cost(const RayJob &j) { return (double)j.G * j.seg * j.n + 4.0 * j.n * j.n / std::max(j.R, 1); }
+double item_cost(const GatherJob &j) { return 256.0 * (j.m + 8); }
+double item_cost(const RampJob &j) { return (double)j.n_det * (j.n_det / 2 + 4); }
+double item_cost(const RotJob &j) { return j.cs ? 256.0 * 4 : 256.0; }
+double item_cost(const RotAdjJob &j) { return 64.0 * 9 * j.copies; }
+double item_cost(const RedJob &j) { return (double)(j.n0 + j.n1); }
+
+// Host image of the device table: appends `bytes` at a 256-byte boundary.
+size_t reserve(std::vector<char> &img, size_t bytes)
+{
+    const size_t off = align256(img.size());
+    img.resize(off + bytes);
+    return off;
+}
+
+template <typename Job>
+void lay_out(const std::vector<Job> &jobs, StageTable &t, std::vector<char> &img)
+{
+    t.njobs = (int)jobs.size();
+    std::vector<long long> first(jobs.size() + 1, 0);
+    double total_cost = 0.0;
+    for (size_t i = 0; i < jobs.size(); i++) {
+        first[i + 1] = first[i] + jobs[i].items;
+        total_cost += item_cost(jobs[i]) * (double)jobs[i].items;
+    }
+    t.total = first.back();
+    // XCD ranges: cut the item sequence where the running cost first reaches
+    // x/8 of the total (items of a job all cost the same)
+    std::vector<long long> xr(kXcds + 1, t.total);
+    xr[0] = 0;
+    {
+        double run = 0.0;
+        int x = 1;
+        for (size_t i = 0; i < jobs.size() && x < kXcds; i++) {
+            const double c = item_cost(jobs[i]);
+            const long long cnt = jobs[i].items;
+            while (x < kXcds) {
+                const double target = total_cost * x / kXcds;
+                if (run + c * (double)cnt < target) break;
+                long long k = c > 0 ? (long long)std::ceil((target - run) / c) : 0;
+                k = std::max(0LL, std::min(k, cnt));
+                xr[x++] = first[i] + k;
+            }
+            run += c * (double)cnt;
+        }
+        for (int q = 1; q <= kXcds; q++) xr[q] = std::max(xr[q], xr[q - 1]);
+    }
+    long long widest = 0;
+    for (int x = 0; x < kXcds; x++) widest = std::max(widest, xr[x + 1] - xr[x]);
+    t.grid_static = (long long)kXcds * widest;
+    // persistent draws: about 16 draws per resident workgroup of an XCD
+    // (32 CUs x up to 8 workgroups), at most 64 items per draw
+    t.chunk = (int)std::max(1LL, std::min(64LL, widest / (32LL * 8 * 16)));
+    t.off_jobs = reserve(img, sizeof(Job) * std::max<size_t>(jobs.size(), 1));
+    if (!jobs.empty()) std::memcpy(img.data() + t.off_jobs, jobs.data(), sizeof(Job) * jobs.size());
+    t.off_first = reserve(img, sizeof(long long) * first.size());
+    std::memcpy(img.data() + t.off_first, first.data(), sizeof(long long) * first.size());
+    t.off_xr = reserve(img, sizeof(long long) * xr.size());
+    std::memcpy(img.data() + t.off_xr, xr.data(), sizeof(long long) * xr.size());
+}
+
+// Stage-tuning cache: signature -> config.
+struct TuneCache {
+    std::mutex mu;
+    std::unordered_map<std::string, StageCfg> map;
+    std::vector<std::string> loaded_files;
+};
+TuneCache &tune_cache()
+{
+    static TuneCache c;
+    return c;
+}
+
+}  // namespace
+
+struct skei_ei_plan {
+    int device = 0;
+    std::vector<skei_ei_problem> probs;
+    std::vector<EiBuffers> bufs;
+    StageCfg cfg[kStages];
+    StageTable tab[kStages];
+    bool any_grad = false;
+    char *dev = nullptr;
+    size_t dev_bytes = 0;
+    WorkQueue *queues = nullptr;   // one per stage, at the start of dev
+};
+
+namespace {
+
+int plan_build(skei_ei_plan *P)
+{
+    const int fwd_rpt = P->cfg[SKEI_STAGE_FWD].shape > 0 ? P->cfg[SKEI_STAGE_FWD].shape : kDefaultRpt;
+    const int bpt_rpt = P->cfg[SKEI_STAGE_BP_T].shape > 0 ? P->cfg[SKEI_STAGE_BP_T].shape : kDefaultRpt;
+    std::vector<RotJob> rot;
+    std::vector<RayJob> fwd, bpt;
+    std::vector<RampJob> ramp, rampT;
+    std::vector<GatherJob> bp, adj;
+    std::vector<RedJob> red;
+    std::vector<RotAdjJob> radj;
+    StageTable t[kStages];
+    int max_m_bp = 1, max_m_adj = 1;
+    for (size_t i = 0; i < P->probs.size(); i++) {
+        const skei_ei_problem &p = P->probs[i];
+        EiJobs J;
+        int rc = ei_problem_jobs(p, P->bufs[i], fwd_rpt, bpt_rpt, J);
+        if (rc) return rc;
+        rot.push_back(J.rot[0]);
+        rot.push_back(J.rot[1]);
+        fwd.push_back(J.fwd[0]);
+        fwd.push_back(J.fwd[1]);
+        for (int k = 0; k < 2; k++) {
+            t[SKEI_STAGE_FWD].rpt = std::max(t[SKEI_STAGE_FWD].rpt, J.fwd_shape[k].rpt);
+            t[SKEI_STAGE_FWD].shm = std::max(t[SKEI_STAGE_FWD].shm, J.fwd_shape[k].shm);
+        }
+        ramp.push_back(J.ramp);
+        bp.push_back(J.bp);
+        max_m_bp = std::max(max_m_bp, p.m);
+        red.push_back(J.red);
+        if (J.grad) {
+            bpt.push_back(J.bpt);
+            t[SKEI_STAGE_BP_T].rpt = std::max(t[SKEI_STAGE_BP_T].rpt, J.bpt_shape.rpt);
+            t[SKEI_STAGE_BP_T].shm = std::max(t[SKEI_STAGE_BP_T].shm, J.bpt_shape.shm);
+            rampT.push_back(J.rampT);
+            adj.push_back(J.adj[0]);
+            adj.push_back(J.adj[1]);
+            max_m_adj = std::max(max_m_adj, std::max(p.m, p.m_mc));
+            radj.push_back(J.radj);
+        }
+    }
+    // ramp launch shape: rows of up to the widest detector, 256 threads
+    int max_nd = 1;
+    for (const skei_ei_problem &p : P->probs) max_nd = std::max(max_nd, p.geom->n_det);
+    for (int s : {SKEI_STAGE_RAMP, SKEI_STAGE_RAMP_T}) {
+        t[s].ramp_block = 256;
+        t[s].ramp_rpt = (max_nd + 255) / 256;
+        t[s].shm = ramp_shm(max_nd, s == SKEI_STAGE_RAMP_T);
+    }
+    const int gbp = P->cfg[SKEI_STAGE_BP_RESID].shape, gadj = P->cfg[SKEI_STAGE_ADJ].shape;
+    t[SKEI_STAGE_BP_RESID].ga = gbp > 0 ? gbp : gather_groups_auto(max_m_bp);
+    t[SKEI_STAGE_ADJ].ga = gadj > 0 ? gadj : gather_groups_auto(max_m_adj);
+
+    std::vector<char> img;
+    reserve(img, sizeof(WorkQueue) * kStages);   // zero cursors
+    lay_out(rot, t[SKEI_STAGE_ROTATE], img);
+    lay_out(fwd, t[SKEI_STAGE_FWD], img);
+    lay_out(ramp, t[SKEI_STAGE_RAMP], img);
+    lay_out(bp, t[SKEI_STAGE_BP_RESID], img);
+    lay_out(red, t[SKEI_STAGE_REDUCE], img);
+    lay_out(bpt, t[SKEI_STAGE_BP_T], img);
+    lay_out(rampT, t[SKEI_STAGE_RAMP_T], img);
+    lay_out(adj, t[SKEI_STAGE_ADJ], img);
+    lay_out(radj, t[SKEI_STAGE_ROTATE_ADJ], img);
+
+    // (re)upload: nothing of this plan may be in flight
+    if (hipSetDevice(P->device) != hipSuccess) return SKEI_ELAUNCH;
+    if (hipDeviceSynchronize() != hipSuccess) return SKEI_ELAUNCH;
+    if (img.size() > P->dev_bytes) {
+        if (P->dev) hipFree(P->dev);
+        P->dev = nullptr;
+        P->dev_bytes = 0;
+        void *d = nullptr;
+        if (hipMalloc(&d, img.size()) != hipSuccess) return SKEI_ENOMEM;
+        P->dev = static_cast<char *>(d);
+        P->dev_bytes = img.size();
+    }
+    if (hipMemcpy(P->dev, img.data(), img.size(), hipMemcpyHostToDevice) != hipSuccess) return SKEI_ELAUNCH;
+    P->queues = reinterpret_cast<WorkQueue *>(P->dev);
+    for (int s = 0; s < kStages; s++) P->tab[s] = t[s];
+    return SKEI_OK;
+}
+
+template <typename Job>
+JobList<Job> table_list(const skei_ei_plan *P, int s)
+{
+    const StageTable &t = P->tab[s];
+    JobList<Job> L{};
+    L.njobs = t.njobs;
+    L.jobs = reinterpret_cast<const Job *>(P->dev + t.off_jobs);
+    L.first = reinterpret_cast<const long long *>(P->dev + t.off_first);
+    L.xr = reinterpret_cast<const long long *>(P->dev + t.off_xr);
+    L.wq = P->cfg[s].dispatch == SKEI_DISPATCH_PERSISTENT ? P->queues + s : nullptr;
+    L.total = t.total;
+    L.grid_static = t.grid_static;
+    L.chunk = t.chunk;
+    return L;
+}
+
+int run_stage(const skei_ei_plan *P, int s, hipStream_t st)
+{
+    const StageTable &t = P->tab[s];
+    if (t.total <= 0) return SKEI_OK;
+    switch (s) {
+    case SKEI_STAGE_ROTATE: return rotate_run(table_list<RotJob>(P, s), st);
+    case SKEI_STAGE_FWD: return ray_run(kRayFwd, false, t.rpt, t.shm, table_list<RayJob>(P, s), st);
+    case SKEI_STAGE_RAMP: return ramp_run(false, t.ramp_rpt, t.ramp_block, t.shm, table_list<RampJob>(P, s), st);
+    case SKEI_STAGE_BP_RESID: return gather_run(kGatherBackproject, t.ga, table_list<GatherJob>(P, s), st);
+    case SKEI_STAGE_REDUCE: return reduce_run(table_list<RedJob>(P, s), st);
+    case SKEI_STAGE_BP_T: return ray_run(kRayBpT, true, t.rpt, t.shm, table_list<RayJob>(P, s), st);
+    case SKEI_STAGE_RAMP_T: return ramp_run(true, t.ramp_rpt, t.ramp_block, t.shm, table_list<RampJob>(P, s), st);
+    case SKEI_STAGE_ADJ: return gather_run(kGatherJosephAdj, t.ga, table_list<GatherJob>(P, s), st);
+    case SKEI_STAGE_ROTATE_ADJ: return rotate_adj_run(table_list<RotAdjJob>(P, s), st);
+    default: return SKEI_EINVAL;
+    }
+}
+
+int check_problem(const skei_ei_problem &p)
+{
+    if (!p.geom || !p.x || !p.y || !p.mc_idx || !p.angle_idx || !p.cos_sin || !p.loss) return SKEI_EINVAL;
+    if (p.batch <= 0 || p.m_mc <= 0 || p.m <= 0 || p.copies <= 0) return SKEI_EINVAL;
+    if ((size_t)p.batch * p.copies > 65535) return SKEI_ERANGE;
+    return SKEI_OK;
+}
+
+// Signature of a stage's work: the sizes of every problem, not its pointers.
+std::string stage_signature(const skei_ei_plan *P, int s)
+{
+    std::string sig = "s" + std::to_string(s);
+    unsigned long long h = 1469598103934665603ULL;
+    auto mix = [&](long long v) {
+        for (int i = 0; i < 8; i++) {
+            h ^= (unsigned long long)((v >> (8 * i)) & 0xff);
+            h *= 1099511628211ULL;
+        }
+    };
+    for (const skei_ei_problem &p : P->probs) {
+        mix(p.geom->n);
+        mix(p.geom->n_angles);
+        mix(p.geom->n_det);
+        mix(p.batch);
+        mix(p.m_mc);
+        mix(p.m);
+        mix(p.copies);
+        mix(p.grad != nullptr);
+    }
+    char buf[32];
+    std::snprintf(buf, sizeof buf, ":%016llx", h);
+    return sig + buf;
+}
+
+void cache_load(const char *path)
+{
+    TuneCache &c = tune_cache();
+    std::lock_guard<std::mutex> lock(c.mu);
+    for (const std::string &f : c.loaded_files)
+        if (f == path) return;
+    c.loaded_files.push_back(path);
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char key[128];
+    int d, sh;
+    while (std::fscanf(f, "%127s %d %d", key, &d, &sh) == 3) c.map[key] = StageCfg{d, sh};
+    std::fclose(f);
+}
+
+void cache_store(const char *path, const std::string &key, const StageCfg &cfg)
+{
+    TuneCache &c = tune_cache();
+    std::lock_guard<std::mutex> lock(c.mu);
+    c.map[key] = cfg;
+    if (!path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d\n", key.c_str(), cfg.dispatch, cfg.shape);
+    std::fclose(f);
+}
+
+bool cache_find(const std::string &key, StageCfg &cfg)
+{
+    TuneCache &c = tune_cache();
+    std::lock_guard<std::mutex> lock(c.mu);
+    auto it = c.map.find(key);
+    if (it == c.map.end()) return false;
+    cfg = it->second;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t skei_ei_plan_workspace_bytes(const skei_ei_problem *problems, int count)
+{
+    if (!problems || count <= 0) return 0;
+    size_t total = 0;
+    for (int i = 0; i < count; i++) {
+        const skei_ei_problem &p = problems[i];
+        if (check_problem(p)) return 0;
+        total += align256(ei_workspace_bytes(p.geom, p.batch, p.m_mc, p.m, p.copies));
+    }
+    return total;
+}
+
+int skei_ei_plan_create(const skei_ei_problem *problems, int count, void *work, size_t work_bytes,
+                        skei_ei_plan **out)
+{
+    if (!problems || count <= 0 || !work || !out) return SKEI_EINVAL;
+    *out = nullptr;
+    for (int i = 0; i < count; i++) {
+        int rc = check_problem(problems[i]);
+        if (rc) return rc;
+    }
+    const size_t need = skei_ei_plan_workspace_bytes(problems, count);
+    if (need == 0) return SKEI_EINVAL;
+    if (work_bytes < need) return SKEI_ESPACE;
+    skei_ei_plan *P = new (std::nothrow) skei_ei_plan;
+    if (!P) return SKEI_ENOMEM;
+    // defaults: long ray-driven items run persistent, short items static
+    for (int s = 0; s < kStages; s++)
+        P->cfg[s].dispatch = is_ray_stage(s) ? SKEI_DISPATCH_PERSISTENT : SKEI_DISPATCH_STATIC;
+    if (hipGetDevice(&P->device) != hipSuccess) {
+        delete P;
+        return SKEI_ELAUNCH;
+    }
+    char *w = static_cast<char *>(work);
+    for (int i = 0; i < count; i++) {
+        const skei_ei_problem &p = problems[i];
+        const size_t b = align256(ei_workspace_bytes(p.geom, p.batch, p.m_mc, p.m, p.copies));
+        EiBuffers eb;
+        if (!ei_carve(p.geom, p.batch, p.m_mc, p.m, p.copies, w, b, eb)) {
+            delete P;
+            return SKEI_ESPACE;
+        }
+        w += b;
+        P->probs.push_back(p);
+        P->bufs.push_back(eb);
+        P->any_grad |= p.grad != nullptr;
+    }
+    int rc = plan_build(P);
+    if (rc) {
+        skei_ei_plan_destroy(P);
+        return rc;
+    }
+    *out = P;
+    return SKEI_OK;
+}
+
+int skei_ei_plan_destroy(skei_ei_plan *plan)
+{
+    if (!plan) return SKEI_EINVAL;
+    if (plan->dev) {
+        int cur = 0;
+        hipGetDevice(&cur);
+        hipSetDevice(plan->device);
+        hipDeviceSynchronize();
+        hipFree(plan->dev);
+        hipSetDevice(cur);
+    }
+    delete plan;
+    return SKEI_OK;
+}
+
+int skei_ei_plan_run(skei_ei_plan *plan, void *stream)
+{
+    if (!plan) return SKEI_EINVAL;
+    const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    for (int s = 0; s < kStages; s++) {
+        if (s > SKEI_STAGE_REDUCE && !plan->any_grad) break;
+        int rc = staged(s, st, [&] { return run_stage(plan, s, st); });
+        if (rc) return rc;
+    }
+    return SKEI_OK;
+}
+
+int skei_ei_plan_configure(skei_ei_plan *plan, int stage, int dispatch, int shape)
+{
+    if (!plan || stage < 0 || stage >= kStages) return SKEI_EINVAL;
+    if (dispatch != SKEI_DISPATCH_PERSISTENT && dispatch != SKEI_DISPATCH_STATIC) return SKEI_EINVAL;
+    if (is_ray_stage(stage) && (shape < 0 || shape > 8)) return SKEI_EINVAL;
+    if (is_gather_stage(stage) && !(shape == 0 || shape == 1 || shape == 2 || shape == 4)) return SKEI_EINVAL;
+    if (!is_ray_stage(stage) && !is_gather_stage(stage)) shape = 0;
+    const bool rebuild = plan->cfg[stage].shape != shape;
+    const StageCfg old = plan->cfg[stage];
+    plan->cfg[stage] = StageCfg{dispatch, shape};
+    if (rebuild) {
+        int rc = plan_build(plan);
+        if (rc) {
+            plan->cfg[stage] = old;
+            plan_build(plan);
+            return rc;
+        }
+    }
+    return SKEI_OK;
+}
+
+int skei_ei_plan_get_config(const skei_ei_plan *plan, int stage, int *dispatch, int *shape)
+{
+    if (!plan || stage < 0 || stage >= kStages) return SKEI_EINVAL;
+    if (dispatch) *dispatch = plan->cfg[stage].dispatch;
+    if (shape) {
+        const StageTable &t = plan->tab[stage];
+        *shape = is_ray_stage(stage) ? t.rpt : is_gather_stage(stage) ? t.ga : 0;
+    }
+    return SKEI_OK;
+}
+
+int skei_ei_plan_autotune(skei_ei_plan *plan, void *stream, int reps, const char *cache_path)
+{
+    if (!plan || reps <= 0) return SKEI_EINVAL;
+    const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (cache_path) cache_load(cache_path);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return SKEI_ELAUNCH;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return SKEI_ELAUNCH;
+    }
+    int rc = SKEI_OK;
+    for (int s = 0; s < kStages && rc == SKEI_OK; s++) {
+        if (plan->tab[s].total <= 0) continue;
+        const std::string key = stage_signature(plan, s);
+        StageCfg best;
+        if (cache_find(key, best)) {
+            rc = skei_ei_plan_configure(plan, s, best.dispatch, best.shape);
+            continue;
+        }
+        std::vector<int> shapes{0};
+        if (is_ray_stage(s)) shapes = {1, 2, 3, 4};
+        if (is_gather_stage(s)) shapes = {1, 2, 4};
+        float best_ms = 3.0e38f;
+        best = plan->cfg[s];
+        for (int d : {SKEI_DISPATCH_PERSISTENT, SKEI_DISPATCH_STATIC}) {
+            for (int sh : shapes) {
+                if ((rc = skei_ei_plan_configure(plan, s, d, sh))) break;
+                if ((rc = run_stage(plan, s, st))) break;   // warm-up
+                std::vector<float> ms;
+                for (int r = 0; r < reps && rc == SKEI_OK; r++) {
+                    if (hipEventRecord(e0, st) != hipSuccess) rc = SKEI_ELAUNCH;
+                    if (!rc) rc = run_stage(plan, s, st);
+                    if (!rc && hipEventRecord(e1, st) != hipSuccess) rc = SKEI_ELAUNCH;
+                    if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = SKEI_ELAUNCH;
+                    float t = 0.0f;
+                    if (!rc && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = SKEI_ELAUNCH;
+                    ms.push_back(t);
+                }
+                if (rc) break;
+                std::sort(ms.begin(), ms.end());
+                const float med = ms[ms.size() / 2];
+                if (med < best_ms) {
+                    best_ms = med;
+                    best = StageCfg{d, sh};
+                }
+            }
+            if (rc) break;
+        }
+        if (rc) break;
+        rc = skei_ei_plan_configure(plan, s, best.dispatch, best.shape);
+        if (!rc) cache_store(cache_path, key, best);
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,140 @@
+// Device-side dispatch of a job list (see JobList in skei_internal.h): maps
+// each workgroup to (job, item) pairs and calls the kernel's item body.
+#pragma once
+
+#include "skei_internal.h"
+
+namespace skei {
+
+typedef __attribute__((address_space(4))) const unsigned int cword_t;
+
+// Reads a job from a device table into scalar registers (the table is
+// read-only while kernels run; `at` is wave-uniform).
+template <typename Job>
+__device__ __forceinline__ Job load_job(const Job *table, int at)
+{
+    static_assert(sizeof(Job) % 4 == 0, "job size");
+    Job j;
+    const cword_t *src = (const cword_t *)(table + at);
+    unsigned int *dst = reinterpret_cast<unsigned int *>(&j);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(Job) / 4); i++) dst[i] = src[i];
+    return j;
+}
+
+__device__ __forceinline__ long long uniform64(long long v)
+{
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(unsigned long long)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((unsigned long long)v >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ long long load_ll(const long long *p, int at)
+{
+    const cword_t *w = (const cword_t *)(p + at);
+    return (long long)(((unsigned long long)w[1] << 32) | w[0]);
+}
+
+// Index of the job owning global item g: the largest j with first[j] <= g.
+__device__ __forceinline__ int find_job(const long long *first, int njobs, long long g)
+{
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (load_ll(first, mid) <= g)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Runs body(job, item) for the workgroup's item(s).  body must be executed by
+// every thread of the workgroup (it may hold barriers) and must not assume
+// anything about LDS contents on entry.
+template <typename Job, typename Body>
+__device__ __forceinline__ void for_each_item(const JobList<Job> &L, Body &&body)
+{
+    if (!L.jobs) {
+        const long long Lb = blockIdx.x;
+        const long long per = (L.total + kXcds - 1) / kXcds;
+        const long long pos = Lb / kXcds;
+        const long long item = (Lb % kXcds) * per + pos;
+        if (pos >= per || item >= L.total) return;
+        if (L.ninl > 1 && item >= L.inl_first[1]) {
+            body(L.inl[1], item - L.inl_first[1]);
+        } else {
+            body(L.inl[0], item);
+        }
+        return;
+    }
+    if (!L.wq) {
+        const int x = blockIdx.x % kXcds;
+        const long long g = load_ll(L.xr, x) + blockIdx.x / kXcds;
+        if (g >= load_ll(L.xr, x + 1)) return;
+        const int j = find_job(L.first, L.njobs, g);
+        body(load_job(L.jobs, j), g - load_ll(L.first, j));
+        return;
+    }
+    __shared__ long long s_item;
+    const int x0 = blockIdx.x % kXcds;
+    const unsigned chunk = L.chunk > 0 ? (unsigned)L.chunk : 1u;
+    for (int q = 0; q < kXcds; q++) {
+        const int x = (x0 + q) % kXcds;
+        const long long beg = load_ll(L.xr, x), end = load_ll(L.xr, x + 1);
+        if (beg >= end) continue;
+        const unsigned span = (unsigned)(end - beg);
+        for (;;) {
+            __syncthreads();   // the previous item is done with s_item and with LDS
+            if (threadIdx.x == 0) {
+                // a plain load first: exhausted queues are skipped without a
+                // read-modify-write on their (contended) cursor
+                const unsigned seen = __hip_atomic_load(&L.wq->next[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s_item = seen >= span ? end : beg + (long long)atomicAdd(&L.wq->next[x], chunk);
+            }
+            __syncthreads();
+            const long long g0 = uniform64(s_item);
+            if (g0 >= end) break;
+            const long long g1 = g0 + chunk < end ? g0 + chunk : end;
+            for (long long g = g0; g < g1; g++) {
+                if (g > g0) __syncthreads();
+                const int j = find_job(L.first, L.njobs, g);
+                body(load_job(L.jobs, j), g - load_ll(L.first, j));
+            }
+        }
+    }
+    // Every workgroup has drawn past the end of every queue before it counts
+    // itself done, so the last one can reset the cursors for the next launch.
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&L.wq->done, 1u) == gridDim.x - 1) {
+            for (int x = 0; x < kXcds; x++) atomicExch(&L.wq->next[x], 0u);
+            atomicExch(&L.wq->done, 0u);
+        }
+    }
+}
+
+// Workgroups of `kernel` that the current device holds at once (cached).
+int resident_workgroups(const void *kernel, int block, size_t shm);
+
+// Grid size of a launch over L with `block` threads and `shm` dynamic LDS
+// bytes; persistent launches fill the device once (occupancy-limited), but
+// never exceed one workgroup per item.
+template <typename Job>
+inline long long launch_grid(const JobList<Job> &L, const void *kernel, int block, size_t shm)
+{
+    if (!L.jobs) return kXcds * ((L.total + kXcds - 1) / kXcds);
+    if (!L.wq) return L.grid_static;
+    long long grid = L.persistent_grid;
+    if (grid <= 0) {
+        const int per_device = resident_workgroups(kernel, block, shm);
+        if (per_device <= 0) return -1;
+        grid = per_device;
+    }
+    if (grid > L.total) grid = L.total;
+    grid = kXcds * ((grid + kXcds - 1) / kXcds);
+    return grid;
+}
+
+}  // namespace skei

@@ -100,3 +100,100 @@ def ei_loss_autograd(x, y, geom: ops.Geometry, sketch, cos_sin, lam: float = 1.0
     w = ops.fbp(ops.radon_fwd(z, geom, sk), geom, sk)
     r = z - w
     return (r_mc.double() ** 2).sum() + (lam / c) * (r.double() ** 2).sum()
+
+
+class EIProblem:
+    """One problem of a batched plan: the inputs of an ``EIStep`` call.
+
+    x: image batch [B,N,N]; y: full sinogram [B,N_theta,N_det]; both device
+    float32 and kept alive (and in place) for the plan's lifetime -- the plan
+    binds their addresses.  ``grad=False`` asks for the loss only.
+    """
+
+    def __init__(self, geom: ops.Geometry, x, y, sketch, cos_sin, lam: float = 1.0, mc=None, grad: bool = True):
+        self.geom = geom
+        self.x = ops._img(geom, x)
+        y3 = y.unsqueeze(0) if y.dim() == 2 else y
+        ops._check(y3, torch.float32, geom.device, "y")
+        if tuple(y3.shape) != (self.x.shape[0], geom.n_angles, geom.n_det):
+            raise ValueError("y must be the full sinogram [B, N_theta, N_det] of the image batch")
+        self.y = y3
+        self.sk = ops._as_sketch(geom, sketch)
+        self.mc = ops._as_sketch(geom, mc)
+        self.cs = cos_sin if isinstance(cos_sin, torch.Tensor) else ops.cos_sin_tensor(cos_sin, geom.device)
+        self.lam = float(lam)
+        self.want_grad = bool(grad)
+        self.grad = torch.empty_like(self.x) if grad else None
+
+    def record(self, loss_ptr: int) -> capi.EiProblem:
+        h = self.geom.handle
+        return capi.EiProblem(h.value if isinstance(h, ctypes.c_void_p) else h, self.x.shape[0],
+                              self.x.data_ptr(), self.y.data_ptr(), self.mc.dev.data_ptr(), self.mc.m,
+                              self.sk.dev.data_ptr(), self.sk.m, self.cs.shape[0], self.cs.data_ptr(), self.lam,
+                              loss_ptr, self.grad.data_ptr() if self.grad is not None else None)
+
+
+class EIPlan:
+    """Batched EI step over problems of different sizes (skei_ei_plan_*).
+
+    Every stage of the step runs as one launch for all problems; problem i's
+    loss lands in ``losses[i]`` and its gradient in ``problems[i].grad``,
+    bitwise equal to what ``EIStep`` gives for it alone.
+    """
+
+    def __init__(self, problems: list[EIProblem]):
+        if not problems:
+            raise ValueError("a plan needs at least one problem")
+        dev = problems[0].geom.device
+        self.problems = list(problems)
+        self.losses = torch.zeros(len(problems), dtype=torch.float64, device=dev)
+        base = self.losses.data_ptr()
+        self._recs = (capi.EiProblem * len(problems))(*[p.record(base + 8 * i) for i, p in enumerate(problems)])
+        nb = capi.query("skei_ei_plan_workspace_bytes", self._recs, len(problems))
+        if nb == 0:
+            raise ValueError("invalid problem list")
+        self.workspace_bytes = int(nb)
+        self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=dev)
+        h = ctypes.c_void_p()
+        capi.call("skei_ei_plan_create", self._recs, len(problems), ops._ptr(self._ws), self.workspace_bytes,
+                  ctypes.byref(h))
+        self._h = h
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("plan is closed")
+        return self._h
+
+    def run(self):
+        capi.call("skei_ei_plan_run", self.handle, ops._stream())
+        return self.losses, [p.grad for p in self.problems]
+
+    def configure(self, stage: str | int, dispatch: int, shape: int = 0):
+        s = capi.STAGES.index(stage) if isinstance(stage, str) else int(stage)
+        capi.call("skei_ei_plan_configure", self.handle, s, int(dispatch), int(shape))
+
+    def config(self, stage: str | int):
+        s = capi.STAGES.index(stage) if isinstance(stage, str) else int(stage)
+        d, sh = ctypes.c_int(), ctypes.c_int()
+        capi.call("skei_ei_plan_get_config", self.handle, s, ctypes.byref(d), ctypes.byref(sh))
+        return d.value, sh.value
+
+    def autotune(self, reps: int = 5, cache_path: str | None = None):
+        """Times every stage's (dispatch, shape) candidates and keeps the best."""
+        self.run()
+        capi.call("skei_ei_plan_autotune", self.handle, ops._stream(), int(reps),
+                  cache_path.encode() if cache_path else None)
+        return {name: self.config(name) for name in capi.STAGES}
+
+    def close(self):
+        if self._h is not None:
+            torch.cuda.synchronize(self._ws.device)
+            capi.call("skei_ei_plan_destroy", self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -102,3 +102,27 @@ def add_relative_noise(y_clean: np.ndarray, z: np.ndarray, rel: float = 0.01) ->
 
 def uniform(shape, seed: int, lo: float = 0.0, hi: float = 1.0) -> np.ndarray:
     return rng(seed).uniform(lo, hi, shape)
+
+
+SEED_PROBLEMS = 6000
+
+
+def uneven_problems(count: int = 64, sizes=(128, 256, 512), angles=(90, 720), ratios=(2, 4, 8), copies: int = 8,
+                    seed: int = SEED_PROBLEMS) -> list[dict]:
+    """A seeded list of uneven EI problems (the batched-plan workload):
+    N drawn from `sizes`, N_theta ~ U{angles[0]..angles[1]},
+    N_det = ceil(sqrt(2) N) + 1, sketch size m = N_theta // ratio with ratio
+    drawn from `ratios` (a random subset, ascending), `copies` rotations.
+    Each entry also carries its own seeds for the phantom, sketch, rotations
+    and noise."""
+    g = rng(seed)
+    out = []
+    for i in range(count):
+        n = int(g.choice(sizes))
+        na = int(g.integers(angles[0], angles[1] + 1))
+        ratio = int(g.choice(ratios))
+        out.append(dict(n=n, n_angles=na, n_det=int(np.ceil(np.sqrt(2.0) * n)) + 1, ratio=ratio,
+                        m=max(1, na // ratio), copies=copies, phantom_seed=SEED_PHANTOM + 100 * i,
+                        sketch_seed=SEED_SKETCH + 100 * i, rotation_seed=SEED_ROTATION + 100 * i,
+                        noise_seed=SEED_NOISE + 100 * i))
+    return out
