@@ -1,15 +1,23 @@
 """Benchmark: sketched EI loss forward+backward step on one MI355X.
 
-Workload (the EI operator step): one 256 x 256 float32 ellipse phantom, 360
-angles in [0, pi), 363 unit detectors, y = A x_true + N(0, (0.01 max)^2),
-x = FBP(y) as the image under evaluation, 16 copies rotated by seeded
-phi ~ U[0, 2 pi), a seeded random quarter sketch (m = 90), lambda = 1.  One
-step is skei_ei_loss_grad: T, A_S, H, B_S (+ residual/loss), A (MC residual),
-reduction, then B_S^T, H, A_S^T, A^T, T^T for the gradient.
+Headline workload (the EI operator step): one 256 x 256 float32 ellipse
+phantom, 360 angles in [0, pi), 363 unit detectors, y = A x_true +
+N(0, (0.01 max)^2), x = FBP(y) as the image under evaluation, 16 copies
+rotated by seeded phi ~ U[0, 2 pi), a seeded random quarter sketch (m = 90),
+lambda = 1.  One step is one run of an autotuned one-problem EI plan
+(skei_ei_plan_run): T (and x^T), A_S on the copies with the MC residual
+y - A x, H, r = z - (pi/m) B_S H A_S z, the loss, then B_S^T, H, A_S^T with
+A^T r_MC, and T^T for the gradient -- nine launches.
 
 value = projector rays per step / step time, in GRays/s: a step evaluates
 the full-scan A and the sketched A_S on every copy once forward and once
 adjoint, i.e. 2 * (N_theta + C*m) * N_det rays.
+
+Extra legs (same JSON line): "batched" -- 64 uneven problems in one plan vs
+one call per problem; "serving" -- Poisson-arriving adaptation jobs under an
+HBM budget, continuous batching vs per-call, p50/p99 latency; "cpu_baseline"
+and "parity" -- the FP64 oracle timed on the host and compared with the
+device on oracle-made inputs.
 
 Prints ONE JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
 """
@@ -51,6 +59,12 @@ def parse():
     ap.add_argument("--workload", default="ei256", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--no-batched", action="store_true", help="skip the uneven 64-problem leg")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-jobs", type=int, default=12)
+    ap.add_argument("--serve-rate", type=float, default=1.5, help="Poisson arrival rate, jobs per second")
+    ap.add_argument("--budget-gb", type=float, default=4.0, help="HBM budget of the serving leg")
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (text)")
     return ap.parse_args()
 
 
@@ -75,6 +89,62 @@ def algorithmic_flops(stage, w, widths):
     return 0.0
 
 
+def ei_inputs(geom, w, dev):
+    """Seeded EI inputs made on the device: phantom, y = A x + 1 % noise, x0 = FBP(y)."""
+    import torch
+
+    from paper_2411_05771_amd import ops, synth
+    xt = torch.from_numpy(synth.phantom_batch(w["n"], w["batch"])).to(dev)
+    y_clean = ops.radon_fwd_(geom, xt, geom.full())
+    z = torch.from_numpy(synth.std_noise(tuple(y_clean.shape))).to(dev, torch.float32)
+    y = (y_clean + 0.01 * y_clean.max() * z).contiguous()
+    x0 = ops.fbp_(geom, y, geom.full()).contiguous()
+    return x0, y
+
+
+def probe_stages(run, reps=5):
+    """Median duration (ms) of every stage of `run` (HIP events around each launch)."""
+    import torch
+
+    from paper_2411_05771_amd import capi
+    stream = torch.cuda.current_stream()
+    out = {}
+    for s, name in enumerate(capi.STAGES):
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for e0, e1 in evs:
+            e0.record(stream)
+            e1.record(stream)
+        for e0, e1 in evs:
+            capi.call("skei_probe_set", s, e0._as_parameter_, e1._as_parameter_)
+            run()
+        torch.cuda.synchronize()
+        out[name] = statistics.median(e0.elapsed_time(e1) for e0, e1 in evs)
+    capi.call("skei_probe_set", -1, None, None)
+    return out
+
+
+def timed_steps(run, steps, probe_stage):
+    """Times exactly `steps` calls of `run` (host clock, synchronised on both
+    sides) while HIP events bracket stage `probe_stage` of every step."""
+    import torch
+
+    from paper_2411_05771_amd import capi
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for e0, e1 in evs:
+        e0.record(stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e0, e1 in evs:
+        capi.call("skei_probe_set", probe_stage, e0._as_parameter_, e1._as_parameter_)
+        run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    capi.call("skei_probe_set", -1, None, None)
+    return (t1 - t0) * 1e3 / steps, statistics.mean(e0.elapsed_time(e1) for e0, e1 in evs)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -95,54 +165,30 @@ def main():
 
     # ---------------------------------------------------------- inputs (seeded, resident in HBM)
     geom = ops.Geometry(n, na, nd)
-    xt = torch.from_numpy(synth.phantom_batch(n, b)).to(dev)
-    y_clean = ops.radon_fwd_(geom, xt, geom.full())
-    z = torch.from_numpy(synth.std_noise(tuple(y_clean.shape))).to(dev, torch.float32)
-    y = (y_clean + 0.01 * y_clean.max() * z).contiguous()
-    x0 = ops.fbp_(geom, y, geom.full()).contiguous()
+    x0, y = ei_inputs(geom, w, dev)
     idx = synth.random_sketch(na, m)
-    cs_host = synth.cos_sin(synth.rotation_angles(c))
-    cs = torch.from_numpy(cs_host.astype(np.float32)).to(dev)
-    step = ei.EIStep(geom, y, geom.sketch(idx), cs, lam)
-    grad = torch.empty_like(x0)
+    cs = torch.from_numpy(synth.cos_sin(synth.rotation_angles(c)).astype(np.float32)).to(dev)
+    sketch = geom.sketch(idx)
     widths = np.maximum(np.abs(np.cos(math.pi * idx / na)), np.abs(np.sin(math.pi * idx / na)))
 
-    for _ in range(args.warmup):
-        step(x0, grad)
-    torch.cuda.synchronize()
+    # the product path: a one-problem EI plan, autotuned (cached per shape)
+    plan = ei.EIPlan([ei.EIProblem(geom, x0, y, sketch, cs, lam)])
+    tuned = plan.autotune(reps=5, cache_path=args.tune_cache)
+    # the one-call entry point, for reference
+    single = ei.EIStep(geom, y, sketch, cs, lam)
+    grad = torch.empty_like(x0)
 
-    # ---------------------------------------------------------- per-stage durations (untimed pass)
-    stream = torch.cuda.current_stream()
-    stage_ms = {}
-    for s, name in enumerate(capi.STAGES):
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
-        for e0, e1 in evs:
-            e0.record(stream)
-            e1.record(stream)
-        for e0, e1 in evs:
-            capi.call("skei_probe_set", s, e0._as_parameter_, e1._as_parameter_)
-            step(x0, grad)
-        torch.cuda.synchronize()
-        stage_ms[name] = statistics.median(e0.elapsed_time(e1) for e0, e1 in evs)
-    capi.call("skei_probe_set", -1, None, None)
+    for _ in range(args.warmup):
+        plan.run()
+        single(x0, grad)
+    torch.cuda.synchronize()
+    stage_ms = probe_stages(plan.run)
     dominant = max(stage_ms, key=stage_ms.get)
     dom_id = capi.STAGES.index(dominant)
 
     # ---------------------------------------------------------- timed region
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    for e0, e1 in evs:
-        e0.record(stream)
-        e1.record(stream)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for e0, e1 in evs:
-        capi.call("skei_probe_set", dom_id, e0._as_parameter_, e1._as_parameter_)
-        step(x0, grad)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    capi.call("skei_probe_set", -1, None, None)
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    dom_ms = statistics.mean(e0.elapsed_time(e1) for e0, e1 in evs)
+    ms_per_step, dom_ms = timed_steps(plan.run, args.steps, dom_id)
+    single_ms, _ = timed_steps(lambda: single(x0, grad), max(5, args.steps // 2), -1)
 
     rays_per_step = 2.0 * (na + c * m) * nd * b
     value = rays_per_step / (ms_per_step * 1e-3) / 1e9
@@ -153,8 +199,10 @@ def main():
         "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
         "frac_nonpacked": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4),
         "launch_ms": round(dom_ms, 5), "traffic": traffic_for(dominant),
+        "gather_equiv_hbm_frac": round(gather_equiv_bytes(dominant, w, widths) / (dom_ms * 1e-3) / 1e9
+                                       / PEAK_HBM_GBS, 4),
     }
-
+    fwd_adj_ms = stage_ms["fwd"] + stage_ms["adj"]
     out = {
         "metric": METRIC, "value": round(value, 4), "unit": "GRays/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True, "scaling": "weak",
@@ -163,12 +211,90 @@ def main():
                    "n_det": nd, "copies": c, "sketch_m": m, "batch": b, "lambda": lam,
                    "rays_per_step": int(rays_per_step)},
         "ei_step_ms": round(ms_per_step, 5),
+        "ei_step_ms_single_call": round(single_ms, 5),
+        "sketched_fwd_adj_grays": round(rays_per_step / (fwd_adj_ms * 1e-3) / 1e9, 4),
         "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
+        "tuned": {k: list(v) for k, v in tuned.items()},
         "roofline": roofline,
     }
+    plan.close()
+    if not args.no_batched:
+        out["batched"] = batched_leg(args)
+    if not args.no_serving:
+        out["serving"] = serving_leg(args)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(x0, y, idx, cs, lam, na, rays_per_step, args.cpu_seconds)
+        out["cpu_baseline"], out["parity"] = cpu_baseline(w, idx, args.cpu_seconds, rays_per_step)
     print(json.dumps(out), flush=True)
+
+
+def gather_equiv_bytes(stage, w, widths):
+    """4 bytes per tap read plus 4 per output written: the bytes the stage
+    would move if every tap came from HBM (the gather-equivalent traffic)."""
+    return 2.0 * algorithmic_flops(stage, w, widths)   # 2 flops per tap -> 4 B per tap; outputs are negligible
+
+
+def batched_leg(args):
+    """The uneven batched workload: 64 problems (N in {128, 256, 512},
+    N_theta ~ U{90..720}, N_det = ceil(sqrt 2 N) + 1, ratio in {2, 4, 8},
+    8 copies), one autotuned plan vs one fused call per problem."""
+    import torch
+
+    from paper_2411_05771_amd import ei, ops, synth
+    dev = torch.device("cuda", 0)
+    specs = synth.uneven_problems()
+    probs = []
+    for p in specs:
+        g = ops.Geometry(p["n"], p["n_angles"], p["n_det"])
+        w = dict(n=p["n"], batch=1)
+        x0, y = ei_inputs(g, w, dev)
+        sk = g.sketch(synth.random_sketch(p["n_angles"], p["m"], p["sketch_seed"]))
+        cs = torch.from_numpy(synth.cos_sin(synth.rotation_angles(p["copies"], p["rotation_seed"]))
+                              .astype(np.float32)).to(dev)
+        probs.append(ei.EIProblem(g, x0, y, sk, cs, 1.0))
+    steps = [ei.EIStep(pr.geom, pr.y, pr.sk, pr.cs, 1.0) for pr in probs]
+
+    def percall():
+        for s_, pr in zip(steps, probs):
+            s_(pr.x, pr.grad)
+    plan = ei.EIPlan(probs)
+    plan.autotune(reps=3, cache_path=args.tune_cache)
+    reps = 5
+    for _ in range(2):
+        plan.run()
+        percall()
+    plan_ms, _ = timed_steps(plan.run, reps, -1)
+    call_ms, _ = timed_steps(percall, reps, -1)
+    rays = sum(2.0 * (p["n_angles"] + p["copies"] * p["m"]) * p["n_det"] for p in specs)
+    plan.close()
+    return {"workload": "uneven_64_problems_8copies", "problems": len(specs), "plan_ms": round(plan_ms, 4),
+            "per_problem_calls_ms": round(call_ms, 4), "speedup": round(call_ms / plan_ms, 3),
+            "plan_grays": round(rays / (plan_ms * 1e-3) / 1e9, 4), "launches_per_step": {"plan": 9,
+                                                                                        "per_problem": 9 * len(specs)}}
+
+
+def serving_leg(args):
+    """Poisson-arriving test-time adaptation jobs (N in {256, 512, 1024},
+    N_theta ~ U{180..1440}, ratio in {2, 4, 8}, 16 copies, 50 iterations)
+    under an HBM budget: continuous batching vs per-call launches on the
+    same arrivals."""
+    from paper_2411_05771_amd import serve, synth
+    specs = synth.poisson_jobs(args.serve_jobs, rate=args.serve_rate)
+    budget = int(args.budget_gb * (1 << 30))
+    res = {"workload": f"poisson_{args.serve_jobs}_jobs_rate{args.serve_rate}", "budget_gb": args.budget_gb,
+           "jobs": args.serve_jobs, "rate_jobs_per_s": args.serve_rate}
+    rays = sum(serve.job_rays(s) for s in specs)
+    for name, batched in (("batched", True), ("per_call", False)):
+        ex = serve.GpuExecutor(batched=batched)
+        ex.prepare(specs)
+        rep = serve.Server(ex, budget).run(specs)
+        ex.close()
+        res[name] = {"p50_s": round(rep.percentile(50), 4), "p99_s": round(rep.percentile(99), 4),
+                     "makespan_s": round(rep.makespan, 3), "grays": round(rays / rep.makespan / 1e9, 4),
+                     "done": len(rep.done), "rejected": len(rep.rejected), "iterations": rep.iterations,
+                     "max_batch": max(rep.batch_sizes) if rep.batch_sizes else 0,
+                     "peak_gb": round(rep.peak_bytes / (1 << 30), 3)}
+        print(f"[serving] {name}: {res[name]}", file=sys.stderr, flush=True)
+    return res
 
 
 def traffic_for(kernel):
@@ -196,23 +322,40 @@ def source_sha():
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(x0, y, idx, cs, lam, na, rays_per_step, target_s):
-    """The FP64 oracle (as it stands) on the same inputs: whole EI steps,
-    repeated until about `target_s` seconds of work."""
+def cpu_baseline(w, idx, target_s, rays_per_step):
+    """The FP64 oracle (as it stands) timed on whole EI steps of the workload,
+    repeated until about `target_s` seconds of work; its inputs are made by
+    the oracle itself (phantom, y = A x + 1 % noise, x0 = FBP(y)), and the
+    same step on the device is checked against it (the parity sample)."""
+    import torch
+
     import oracle
-    xh = x0.detach().cpu().numpy().astype(np.float64)
-    yh = y.detach().cpu().numpy().astype(np.float64)
-    csh = cs.detach().cpu().numpy().astype(np.float64)
+    from paper_2411_05771_amd import ei, ops, synth
+    n, na, nd, c, lam = w["n"], w["n_angles"], w["n_det"], w["copies"], w["lam"]
+    xt = synth.phantom_batch(n, w["batch"]).astype(np.float64)
+    yc = oracle.radon_fwd(xt, na, nd)
+    y = synth.add_relative_noise(yc, synth.std_noise(yc.shape)).astype(np.float32).astype(np.float64)
+    x0 = oracle.fbp(y, n, na).astype(np.float32).astype(np.float64)
+    cs = synth.cos_sin(synth.rotation_angles(c)).astype(np.float32).astype(np.float64)
     reps, t_total = 0, 0.0
     while t_total < target_s and reps < 10:
         t0 = time.perf_counter()
-        oracle.ei_loss_grad(xh, yh, na, idx, csh, lam)
+        want_l, want_g = oracle.ei_loss_grad(x0, y, na, idx, cs, lam)
         t_total += time.perf_counter() - t0
         reps += 1
     per_step = t_total / reps
-    return {"value": round(rays_per_step / per_step / 1e9, 6), "unit": "GRays/s", "cores": oracle.num_threads(),
+    base = {"value": round(rays_per_step / per_step / 1e9, 6), "unit": "GRays/s", "cores": oracle.num_threads(),
             "kind": "oracle", "sample": f"{reps} full EI steps of the same workload (float64, OpenMP)",
             "s_per_step": round(per_step, 4)}
+    dev = torch.device("cuda", 0)
+    geom = ops.Geometry(n, na, nd)
+    step = ei.EIStep(geom, torch.from_numpy(y.astype(np.float32)).to(dev), geom.sketch(idx),
+                     torch.from_numpy(cs.astype(np.float32)).to(dev), lam)
+    loss, grad = step(torch.from_numpy(x0.astype(np.float32)).to(dev))
+    g = grad.cpu().numpy().astype(np.float64).reshape(want_g.shape)
+    parity = {"loss_relerr": float(abs(loss.item() - want_l) / abs(want_l)),
+              "grad_relerr": float(np.max(np.abs(g - want_g)) / np.max(np.abs(want_g)))}
+    return base, parity
 
 
 if __name__ == "__main__":

@@ -188,7 +188,7 @@ int skei_ei_loss_grad(const skei_geom *g, const float *x, const float *y, int ba
 typedef struct skei_ei_problem {
     const skei_geom *geom;
     int batch;
-    const float *x;             /* [batch][N][N]                         */
+    float *x;                   /* [batch][N][N]; updated when step != 0 */
     const float *y;             /* [batch][N_theta][N_det]               */
     const int32_t *mc_idx;      /* MC angle list, m_mc entries           */
     int m_mc;
@@ -199,6 +199,9 @@ typedef struct skei_ei_problem {
     float lambda;
     double *loss;               /* one device double                     */
     float *grad;                /* [batch][N][N] or NULL                 */
+    float step;                 /* gradient step: after the gradient is  */
+                                /* formed, x -= step * grad (0: x is     */
+                                /* left alone; needs grad)               */
 } skei_ei_problem;
 
 typedef struct skei_ei_plan skei_ei_plan;

@@ -31,6 +31,7 @@ class EiProblem(ctypes.Structure):
         ("geom", c_void_p), ("batch", c_int), ("x", c_void_p), ("y", c_void_p),
         ("mc_idx", c_void_p), ("m_mc", c_int), ("angle_idx", c_void_p), ("m", c_int),
         ("copies", c_int), ("cos_sin", c_void_p), ("lam", c_float), ("loss", c_void_p), ("grad", c_void_p),
+        ("step", c_float),
     ]
 
 

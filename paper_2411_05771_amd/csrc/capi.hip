@@ -168,6 +168,10 @@ int ei_problem_jobs(const skei_ei_problem &p, const EiBuffers &b, int fwd_rpt, i
     J.adj[0] = make_gather_job(g, b.qs, bc, p.angle_idx, m, 1.0f, b.z, b.r, nullptr, nullptr);
     J.adj[1] = make_gather_job(g, b.rmc, batch, p.mc_idx, m_mc, 1.0f, b.amc, nullptr, nullptr, nullptr);
     J.radj = make_rot_adj_job(b.z, batch, copies, n, p.cos_sin, 2.0f * p.lambda / copies, b.amc, -2.0f, p.grad);
+    if (p.step != 0.0f && p.grad) {
+        J.radj.x_upd = p.x;
+        J.radj.step = p.step;
+    }
     return SKEI_OK;
 }
 
@@ -305,7 +309,8 @@ int skei_ei_loss_grad(const skei_geom *g, const float *x, const float *y, int ba
     if ((size_t)batch * copies > 65535) return SKEI_ERANGE;
     EiBuffers b;
     if (!ei_carve(g, batch, m_mc, m, copies, work, work_bytes, b)) return SKEI_ESPACE;
-    const skei_ei_problem p{g, batch, x, y, mc_idx, m_mc, angle_idx, m, copies, cos_sin, lambda, loss, grad};
+    const skei_ei_problem p{g, batch, const_cast<float *>(x), y, mc_idx, m_mc, angle_idx, m, copies, cos_sin,
+                            lambda, loss, grad, 0.0f};
     EiJobs J;
     int rc = ei_problem_jobs(p, b, 0, 0, J);
     if (rc) return rc;

@@ -143,8 +143,10 @@ __device__ __forceinline__ void rotate_adj_item(const RotAdjJob &J, long long it
     if (grp == 0 && in) {
         const float s = ((part[0][px] + part[1][px]) + part[2][px]) + part[3][px];
         float v = J.alpha * s;
-        if (J.add) v = fmaf(J.beta, J.add[(size_t)b * n * n + p], v);
-        J.g[(size_t)b * n * n + p] = v;
+        const size_t o = (size_t)b * n * n + p;
+        if (J.add) v = fmaf(J.beta, J.add[o], v);
+        J.g[o] = v;
+        if (J.x_upd) J.x_upd[o] = fmaf(-J.step, v, J.x_upd[o]);
     }
 }
 

@@ -261,6 +261,7 @@ int check_problem(const skei_ei_problem &p)
     if (!p.geom || !p.x || !p.y || !p.mc_idx || !p.angle_idx || !p.cos_sin || !p.loss) return SKEI_EINVAL;
     if (p.batch <= 0 || p.m_mc <= 0 || p.m <= 0 || p.copies <= 0) return SKEI_EINVAL;
     if ((size_t)p.batch * p.copies > 65535) return SKEI_ERANGE;
+    if (p.step != 0.0f && !p.grad) return SKEI_EINVAL;
     return SKEI_OK;
 }
 

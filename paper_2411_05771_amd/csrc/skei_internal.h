@@ -112,14 +112,17 @@ struct RotJob {
     long long items;
 };
 
-// g[b] = alpha * sum_c T_c^T h[b][c] + beta * add[b].  An item is 64 pixels.
+// g[b] = alpha * sum_c T_c^T h[b][c] + beta * add[b]; then, when x_upd is
+// given, x_upd[b] -= step * g[b].  An item is 64 pixels.
 struct RotAdjJob {
     const float *h;
     const float *cs;
     const float *add;
     float *g;
+    float *x_upd;
     int n, copies;
-    float alpha, beta;
+    float alpha, beta, step;
+    int pad_;
     long long items;
 };
 

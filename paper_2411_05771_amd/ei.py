@@ -107,10 +107,12 @@ class EIProblem:
 
     x: image batch [B,N,N]; y: full sinogram [B,N_theta,N_det]; both device
     float32 and kept alive (and in place) for the plan's lifetime -- the plan
-    binds their addresses.  ``grad=False`` asks for the loss only.
+    binds their addresses.  ``grad=False`` asks for the loss only; ``step``
+    > 0 makes every run end with the gradient step x -= step * grad.
     """
 
-    def __init__(self, geom: ops.Geometry, x, y, sketch, cos_sin, lam: float = 1.0, mc=None, grad: bool = True):
+    def __init__(self, geom: ops.Geometry, x, y, sketch, cos_sin, lam: float = 1.0, mc=None, grad: bool = True,
+                 step: float = 0.0):
         self.geom = geom
         self.x = ops._img(geom, x)
         y3 = y.unsqueeze(0) if y.dim() == 2 else y
@@ -124,13 +126,16 @@ class EIProblem:
         self.lam = float(lam)
         self.want_grad = bool(grad)
         self.grad = torch.empty_like(self.x) if grad else None
+        if step and not grad:
+            raise ValueError("a gradient step needs the gradient")
+        self.step = float(step)   # x -= step * grad after each evaluation (in place)
 
     def record(self, loss_ptr: int) -> capi.EiProblem:
         h = self.geom.handle
         return capi.EiProblem(h.value if isinstance(h, ctypes.c_void_p) else h, self.x.shape[0],
                               self.x.data_ptr(), self.y.data_ptr(), self.mc.dev.data_ptr(), self.mc.m,
                               self.sk.dev.data_ptr(), self.sk.m, self.cs.shape[0], self.cs.data_ptr(), self.lam,
-                              loss_ptr, self.grad.data_ptr() if self.grad is not None else None)
+                              loss_ptr, self.grad.data_ptr() if self.grad is not None else None, self.step)
 
 
 class EIPlan:

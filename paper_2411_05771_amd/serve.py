@@ -1,0 +1,279 @@
+"""Continuous-batching server for test-time EI adaptation jobs.
+
+A job is one measured sinogram y to be reconstructed by test-time EI
+adaptation (Algorithm 2 with the network taken as the identity, so the
+adapted quantity is the image itself): x starts at FBP(y) and takes `iters`
+gradient steps x <- x - eta * grad L(x) on the sketched EI loss, a new
+interleaved sketch S_k (k = iteration mod ratio, Sec. 4.2.1) and a new set
+of rotations per iteration.
+
+Scheduling.  Jobs arrive over time; a job is admitted (FIFO) as soon as it
+has arrived, a slot is free and its device footprint fits in the HBM budget
+beside the jobs already running.  Each server iteration runs ONE step of
+every admitted job: the GPU executor batches them into one EI plan (one
+launch per stage for all jobs, skei_ei_plan_run with the gradient step fused
+into the last kernel), so jobs that arrive while others run join the next
+iteration and their work overlaps on the device.  Finished jobs leave and
+free their memory.  A job's results depend only on its own inputs and
+iteration count -- the plan computes every problem bitwise as it would alone
+-- so a job gives the same answer alone and in any mix.
+
+The scheduler (``Server``) is device-agnostic: it talks to an executor
+(footprint / start / step / finish) and a clock (now / sleep_until), so its
+logic is tested on the CPU with fakes.
+"""
+from __future__ import annotations
+
+import math
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Job:
+    spec: dict
+    arrival: float
+    footprint: int
+    it: int = 0
+    admitted: float | None = None
+    finished: float | None = None
+    state: object = None
+    result: object = None
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+class WallClock:
+    def __init__(self):
+        self.t0 = time.perf_counter()
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def sleep_until(self, t: float):
+        dt = t - self.now()
+        if dt > 0:
+            time.sleep(dt)
+
+
+@dataclass
+class ServeReport:
+    done: list
+    rejected: list
+    iterations: int
+    max_active: int
+    peak_bytes: int
+    makespan: float
+    batch_sizes: list = field(default_factory=list)
+
+    def latencies(self) -> np.ndarray:
+        return np.array([j.latency for j in self.done], dtype=np.float64)
+
+    def percentile(self, q: float) -> float:
+        lat = self.latencies()
+        return float(np.percentile(lat, q)) if lat.size else math.nan
+
+
+class Server:
+    """FIFO admission under a device-memory budget and a slot limit;
+    continuous batching of one iteration of every admitted job per step."""
+
+    def __init__(self, executor, budget_bytes: int, max_active: int = 64, clock=None):
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.max_active = int(max_active)
+        self.clock = clock or WallClock()
+
+    def run(self, specs) -> ServeReport:
+        pending = deque(Job(s, float(s["arrival"]), int(self.ex.footprint(s)))
+                        for s in sorted(specs, key=lambda s: (s["arrival"], s["job"])))
+        active: list[Job] = []
+        done, rejected, sizes = [], [], []
+        used = peak = 0
+        iters = 0
+        start = self.clock.now()
+        while pending or active:
+            now = self.clock.now()
+            while pending and pending[0].arrival <= now:
+                j = pending[0]
+                if j.footprint > self.budget:          # can never fit
+                    rejected.append(pending.popleft())
+                    continue
+                if len(active) >= self.max_active or used + j.footprint > self.budget:
+                    break                                # head of line waits
+                pending.popleft()
+                j.admitted = now
+                j.state = self.ex.start(j.spec)
+                used += j.footprint
+                peak = max(peak, used)
+                active.append(j)
+            if not active:
+                if pending:
+                    self.clock.sleep_until(pending[0].arrival)
+                continue
+            self.ex.step([j.state for j in active])
+            iters += 1
+            sizes.append(len(active))
+            now = self.clock.now()
+            still = []
+            for j in active:
+                j.it += 1
+                if j.it >= j.spec["iters"]:
+                    j.finished = now
+                    j.result = self.ex.finish(j.state)
+                    j.state = None
+                    used -= j.footprint
+                    done.append(j)
+                else:
+                    still.append(j)
+            active = still
+        return ServeReport(done, rejected, iters, self.max_active, peak, self.clock.now() - start, sizes)
+
+
+def step_size(n: int, n_angles_mc: int, lam: float) -> float:
+    """A gradient step below 1/L for the EI loss: the MC term's Hessian
+    2 A^T A has norm <= 2 ||A||_1 ||A||_inf <= 2 (1.5 N_theta)(sqrt(2) N)
+    (Joseph columns sum to <= ~1.5 per angle, rows to <= sqrt(2) N), and the
+    EI term adds at most ~20 lambda."""
+    return 1.0 / (2.0 * 1.5 * math.sqrt(2.0) * n * n_angles_mc + 20.0 * lam)
+
+
+class GpuExecutor:
+    """Runs jobs on the device through the library.
+
+    batched=True : one EI plan over all admitted jobs per iteration (rebuilt
+                   only when the set of jobs changes).
+    batched=False: the per-call baseline -- each job has its own one-problem
+                   plan and the jobs' steps run one after another.
+    Inputs (the measured sinograms) are made once by ``prepare`` and kept in
+    pinned host memory; ``start`` copies a job's sinogram to the device and
+    forms x = FBP(y) there, as a server ingesting a request would.
+    """
+
+    def __init__(self, batched: bool = True, lam: float = 1.0, record_loss: bool = False):
+        import torch
+
+        from . import ops
+        self.torch, self.ops = torch, ops
+        self.dev = torch.device("cuda", torch.cuda.current_device())
+        self.batched = batched
+        self.lam = float(lam)
+        self.record_loss = record_loss
+        self.geoms = {}
+        self.host_y = {}
+        self._plan = None
+        self._plan_key = None
+        self.plan_builds = 0
+
+    # ---------------------------------------------------------------- inputs
+    def geometry(self, spec):
+        key = (spec["n"], spec["n_angles"], spec["n_det"])
+        if key not in self.geoms:
+            self.geoms[key] = self.ops.Geometry(*key, device=self.dev)
+        return self.geoms[key]
+
+    def prepare(self, specs):
+        """Measured sinograms y = A x_true + 1 % noise of each job (device
+        forward projection of its seeded phantom), kept in pinned host memory."""
+        from . import synth
+        torch = self.torch
+        for s in specs:
+            g = self.geometry(s)
+            xt = torch.from_numpy(synth.ellipse_phantom(s["n"], s["phantom_seed"])[None]).to(self.dev)
+            y = self.ops.radon_fwd_(g, xt, g.full())
+            z = torch.from_numpy(synth.std_noise(tuple(y.shape), s["noise_seed"])).to(self.dev, torch.float32)
+            y = (y + 0.01 * y.max() * z).contiguous()
+            self.host_y[s["job"]] = y.cpu().pin_memory()
+        torch.cuda.synchronize()
+
+    def footprint(self, spec) -> int:
+        from . import capi
+        g = self.geometry(spec)
+        n, na, nd, m, c = spec["n"], spec["n_angles"], spec["n_det"], spec["m"], spec["copies"]
+        fake = 256   # sizes only: the query reads no memory
+        rec = (capi.EiProblem * 1)(capi.EiProblem(g.handle.value, 1, fake, fake, fake, na, fake, m, c, fake,
+                                                  self.lam, fake, fake, 0.0))
+        ws = int(capi.query("skei_ei_plan_workspace_bytes", rec, 1))
+        own = 4 * (3 * n * n + na * nd + spec["ratio"] * m + spec["iters"] * c * 2 + m + 2 * c) + 8 * spec["iters"]
+        return ws + own
+
+    # ------------------------------------------------------------ lifecycle
+    def start(self, spec):
+        from . import ei, synth
+        torch, ops = self.torch, self.ops
+        g = self.geometry(spec)
+        y = self.host_y[spec["job"]].to(self.dev, non_blocking=True)
+        x = ops.fbp_(g, y, g.full()).contiguous()
+        na, ratio, m = spec["n_angles"], spec["ratio"], spec["m"]
+        subsets = np.stack([k + ratio * np.arange(m) for k in range(ratio)]).astype(np.int32)
+        st = _JobState()
+        st.spec = spec
+        st.sk_table = torch.from_numpy(subsets).to(self.dev)
+        phis = synth.rotation_angles(spec["iters"] * spec["copies"], spec["rotation_seed"])
+        st.cs_table = torch.from_numpy(synth.cos_sin(phis).reshape(spec["iters"], spec["copies"], 2)).to(
+            self.dev, torch.float32)
+        st.sketch = g.sketch(subsets[0])
+        st.cs = st.cs_table[0].clone()
+        st.it = 0
+        st.eta = step_size(spec["n"], na, self.lam)
+        st.problem = ei.EIProblem(g, x, y, st.sketch, st.cs, self.lam, grad=True, step=st.eta)
+        st.loss = torch.zeros(spec["iters"], dtype=torch.float64, device=self.dev) if self.record_loss else None
+        st.own_plan = None if self.batched else ei.EIPlan([st.problem])
+        return st
+
+    def _inputs(self, st):
+        # this iteration's sketch S_k (k = it mod ratio) and rotations
+        st.sketch.dev.copy_(st.sk_table[st.it % st.spec["ratio"]])
+        st.cs.copy_(st.cs_table[st.it])
+
+    def step(self, states):
+        from . import ei
+        for st in states:
+            self._inputs(st)
+        if self.batched:
+            key = tuple(id(st) for st in states)
+            if key != self._plan_key:
+                if self._plan is not None:
+                    self._plan.close()
+                self._plan = ei.EIPlan([st.problem for st in states])
+                self._plan_key = key
+                self.plan_builds += 1
+            self._plan.run()
+            if self.record_loss:
+                for i, st in enumerate(states):
+                    st.loss[st.it].copy_(self._plan.losses[i])
+        else:
+            for st in states:
+                st.own_plan.run()
+                if self.record_loss:
+                    st.loss[st.it].copy_(st.own_plan.losses[0])
+        for st in states:
+            st.it += 1
+        self.torch.cuda.synchronize()
+
+    def finish(self, st):
+        out = {"x": st.problem.x.clone(), "loss": st.loss}
+        if st.own_plan is not None:
+            st.own_plan.close()
+        return out
+
+    def close(self):
+        if self._plan is not None:
+            self._plan.close()
+            self._plan = None
+            self._plan_key = None
+
+
+class _JobState:
+    pass
+
+
+def job_rays(spec) -> float:
+    """Projector rays one iteration of a job evaluates: A on the full scan
+    and A_S on every copy, forward and adjoint."""
+    return 2.0 * (spec["n_angles"] + spec["copies"] * spec["m"]) * spec["n_det"] * spec["iters"]

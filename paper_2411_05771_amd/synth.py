@@ -126,3 +126,25 @@ def uneven_problems(count: int = 64, sizes=(128, 256, 512), angles=(90, 720), ra
                         sketch_seed=SEED_SKETCH + 100 * i, rotation_seed=SEED_ROTATION + 100 * i,
                         noise_seed=SEED_NOISE + 100 * i))
     return out
+
+
+def poisson_jobs(count: int, rate: float, sizes=(256, 512, 1024), angles=(180, 1440), ratios=(2, 4, 8),
+                 copies: int = 16, iters: int = 50, seed: int = SEED_ARRIVALS) -> list[dict]:
+    """A seeded stream of test-time-adaptation jobs: Poisson arrivals at
+    `rate` jobs per second (exponential gaps, first job at t = 0), N drawn
+    from `sizes`, N_theta ~ U{angles}, N_det = ceil(sqrt(2) N), sketch ratio
+    from `ratios` (interleaved subsets of N_theta // ratio angles), `copies`
+    rotations and `iters` iterations each, with per-job seeds."""
+    g = rng(seed)
+    t = 0.0
+    out = []
+    for i in range(count):
+        if i > 0:
+            t += float(g.exponential(1.0 / rate))
+        n = int(g.choice(sizes))
+        na = int(g.integers(angles[0], angles[1] + 1))
+        ratio = int(g.choice(ratios))
+        out.append(dict(job=i, arrival=t, n=n, n_angles=na, n_det=int(np.ceil(np.sqrt(2.0) * n)), ratio=ratio,
+                        m=max(1, na // ratio), copies=copies, iters=iters, phantom_seed=SEED_PHANTOM + 7919 * (i + 1),
+                        rotation_seed=SEED_ROTATION + 7919 * (i + 1), noise_seed=SEED_NOISE + 7919 * (i + 1)))
+    return out

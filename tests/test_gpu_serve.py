@@ -1,0 +1,136 @@
+"""The continuous-batching server on the device (paper_2411_05771_amd.serve).
+
+1. A job's result (its final image and its loss at every iteration) is
+   bitwise the same when it runs alone, in a mix that other jobs join and
+   leave while it runs, and under the per-call executor (each job's own
+   one-problem plan, no batching).  Admission is driven by a step clock so
+   the mix is reproducible: job j arrives just before iteration a_j.
+2. A small job's whole trajectory -- x_0 = FBP(y), then x <- x - eta grad L
+   with the interleaved sketch S_(k mod ratio) and the iteration's rotations
+   -- matches the FP64 oracle run on the same inputs within the EI bar.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import f32, host, relerr
+from paper_2411_05771_amd import serve, synth
+
+pytestmark = pytest.mark.gpu
+
+
+class StepClock:
+    """Time = number of finished iterations (admission happens between them)."""
+
+    def __init__(self):
+        self.t = 0.0
+
+    def now(self):
+        return self.t
+
+    def sleep_until(self, t):
+        self.t = max(self.t, t)
+
+
+class ClockedExecutor:
+    def __init__(self, inner, clock):
+        self.inner, self.clock = inner, clock
+
+    def footprint(self, spec):
+        return self.inner.footprint(spec)
+
+    def start(self, spec):
+        return self.inner.start(spec)
+
+    def step(self, states):
+        self.inner.step(states)
+        self.clock.t += 1.0
+
+    def finish(self, st):
+        return self.inner.finish(st)
+
+
+def small_jobs():
+    specs = synth.poisson_jobs(5, rate=1.0, sizes=(48, 64, 96), angles=(40, 120), ratios=(2, 4), copies=4, iters=6,
+                               seed=5100)
+    for i, s in enumerate(specs):
+        s["arrival"] = [0.0, 0.0, 1.5, 2.5, 7.5][i]    # joins after iterations 0, 2, 3, 8
+    return specs
+
+
+def serve_jobs(specs, batched, budget=1 << 34, max_active=64, host_y=None):
+    ex = serve.GpuExecutor(batched=batched, record_loss=True)
+    if host_y is None:
+        ex.prepare(specs)
+    else:
+        ex.host_y.update(host_y)
+    clock = StepClock()
+    rep = serve.Server(ClockedExecutor(ex, clock), budget, max_active=max_active, clock=clock).run(specs)
+    ex.close()
+    return rep, ex
+
+
+def test_job_results_same_alone_in_mix_and_per_call(skei):
+    specs = small_jobs()
+    print("\n[serve] mix of 5 jobs, batched", flush=True)
+    mix, ex_mix = serve_jobs(specs, batched=True)
+    assert max(mix.batch_sizes) >= 3, "the jobs never overlapped"
+    assert ex_mix.plan_builds >= 3
+    got = {j.spec["job"]: j.result for j in mix.done}
+    print("[serve] per-call executor", flush=True)
+    percall, _ = serve_jobs(specs, batched=False)
+    for j in percall.done:
+        r = got[j.spec["job"]]
+        assert torch.equal(j.result["x"], r["x"]), f"job {j.spec['job']}: per-call image differs"
+        assert torch.equal(j.result["loss"], r["loss"]), f"job {j.spec['job']}: per-call losses differ"
+    for s in specs:
+        print(f"[serve] job {s['job']} alone (n={s['n']} n_angles={s['n_angles']} ratio={s['ratio']})", flush=True)
+        alone, _ = serve_jobs([dict(s, arrival=0.0)], batched=True)
+        r = got[s["job"]]
+        assert torch.equal(alone.done[0].result["x"], r["x"]), f"job {s['job']}: image differs alone vs mix"
+        assert torch.equal(alone.done[0].result["loss"], r["loss"]), f"job {s['job']}: losses differ alone vs mix"
+        loss = host(r["loss"])
+        assert loss[-1] < loss[0]
+
+
+def test_budget_limits_the_mix(skei):
+    specs = small_jobs()
+    ex = serve.GpuExecutor(batched=True)
+    fp = sorted(ex.footprint(s) for s in specs)
+    budget = fp[-1] + fp[-2]
+    # the most jobs that can ever share the budget: the smallest ones
+    max_fit = max(k for k in range(1, len(fp) + 1) if sum(fp[:k]) <= budget)
+    assert max_fit < len(specs)
+    rep, _ = serve_jobs(specs, batched=True, budget=budget)
+    assert len(rep.done) == len(specs)
+    assert rep.peak_bytes <= budget
+    assert max(rep.batch_sizes) <= max_fit
+
+
+def test_served_trajectory_matches_oracle(skei, orc):
+    s = dict(job=0, arrival=0.0, n=64, n_angles=60, n_det=91, ratio=2, m=30, copies=4, iters=5,
+             phantom_seed=synth.SEED_PHANTOM, rotation_seed=synth.SEED_ROTATION + 11, noise_seed=synth.SEED_NOISE)
+    print(f"\n[serve-oracle] {s}", flush=True)
+    xt = synth.ellipse_phantom(s["n"], s["phantom_seed"]).astype(np.float64)[None]
+    yc = orc.radon_fwd(xt, s["n_angles"], s["n_det"])
+    y = f32(synth.add_relative_noise(yc, synth.std_noise(yc.shape, s["noise_seed"])))
+    rep, _ = serve_jobs([s], batched=True,
+                        host_y={0: torch.from_numpy(y.astype(np.float32)).pin_memory()})
+    res = rep.done[0].result
+    # the oracle's run of the same iterations
+    eta = float(np.float32(serve.step_size(s["n"], s["n_angles"], 1.0)))
+    phis = synth.rotation_angles(s["iters"] * s["copies"], s["rotation_seed"])
+    cs_all = f32(synth.cos_sin(phis)).reshape(s["iters"], s["copies"], 2)
+    x = orc.fbp(y, s["n"], s["n_angles"])
+    losses = []
+    for it in range(s["iters"]):
+        k = it % s["ratio"]
+        idx = (k + s["ratio"] * np.arange(s["m"])).astype(np.int32)
+        loss, g = orc.ei_loss_grad(x, y, s["n_angles"], idx, cs_all[it], 1.0)
+        losses.append(loss)
+        x = x - eta * g
+    e_x = relerr(host(res["x"]), x)
+    e_l = np.max(np.abs(host(res["loss"]) - np.array(losses)) / np.abs(np.array(losses)))
+    print(f"[serve-oracle] final image relerr {e_x:.2e}, losses relerr {e_l:.2e}", flush=True)
+    assert e_x <= 1e-5
+    assert e_l <= 1e-5

@@ -1,0 +1,147 @@
+"""Host logic of the continuous-batching server (paper_2411_05771_amd.serve),
+with a fake clock and a fake executor: admission under the memory budget and
+the slot limit, FIFO order, continuous batching (jobs join between
+iterations), completion after exactly `iters` steps, rejection of jobs that
+can never fit, and idle gaps."""
+import pytest
+
+from paper_2411_05771_amd import serve, synth
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def now(self):
+        return self.t
+
+    def sleep_until(self, t):
+        self.t = max(self.t, t)
+
+
+class FakeExecutor:
+    """Step time = base + per-job cost (batching amortises `base`)."""
+
+    def __init__(self, clock, budget, base=1.0, per_job=0.25):
+        self.clock, self.budget = clock, budget
+        self.base, self.per_job = base, per_job
+        self.steps = []          # (time, [job ids]) per step
+        self.started, self.finished = [], []
+        self.active = {}
+
+    def footprint(self, spec):
+        return spec["bytes"]
+
+    def start(self, spec):
+        self.started.append((self.clock.now(), spec["job"]))
+        self.active[spec["job"]] = spec
+        assert sum(s["bytes"] for s in self.active.values()) <= self.budget
+        return {"job": spec["job"], "it": 0}
+
+    def step(self, states):
+        self.steps.append((self.clock.now(), [s["job"] for s in states]))
+        for s in states:
+            s["it"] += 1
+        self.clock.t += self.base + self.per_job * len(states)
+
+    def finish(self, state):
+        self.finished.append((self.clock.now(), state["job"]))
+        del self.active[state["job"]]
+        return state["it"]
+
+
+def jobs(arrivals, sizes, iters=3):
+    return [dict(job=i, arrival=a, bytes=b, iters=iters) for i, (a, b) in enumerate(zip(arrivals, sizes))]
+
+
+def run(specs, budget, max_active=64, **kw):
+    clock = FakeClock()
+    ex = FakeExecutor(clock, budget, **kw)
+    rep = serve.Server(ex, budget, max_active=max_active, clock=clock).run(specs)
+    return rep, ex
+
+
+def test_every_job_runs_exactly_its_iterations():
+    specs = jobs([0.0, 0.1, 0.2, 5.0], [10, 10, 10, 10], iters=4)
+    rep, ex = run(specs, budget=100)
+    assert sorted(j.spec["job"] for j in rep.done) == [0, 1, 2, 3]
+    assert all(j.result == 4 for j in rep.done)
+    for j in rep.done:
+        assert sum(j.spec["job"] in ids for _, ids in ex.steps) == 4
+        assert j.finished > j.arrival and j.latency > 0
+
+
+def test_continuous_batching_admits_between_iterations():
+    # job 1 arrives while job 0's first step runs (0 .. 1.25): it joins at the next step
+    specs = jobs([0.0, 0.5], [10, 10], iters=3)
+    rep, ex = run(specs, budget=100)
+    assert ex.steps[0][1] == [0]
+    assert ex.steps[1][1] == [0, 1]
+    admitted = {j.spec["job"]: j.admitted for j in rep.done}
+    assert admitted[1] == pytest.approx(ex.steps[1][0])
+    assert max(len(ids) for _, ids in ex.steps) == 2
+
+
+def test_budget_and_fifo_head_of_line():
+    # job 1 (60) does not fit beside job 0 (50) in 100: it waits, and job 2
+    # (10, which would fit) waits behind it -- FIFO
+    specs = jobs([0.0, 0.1, 0.2], [50, 60, 10], iters=2)
+    rep, ex = run(specs, budget=100)
+    order = [jid for _, jid in ex.started]
+    assert order == [0, 1, 2]
+    t_start = dict((jid, t) for t, jid in ex.started)
+    t_fin = dict((jid, t) for t, jid in ex.finished)
+    assert t_start[1] >= t_fin[0]
+    assert t_start[2] >= t_start[1]
+    assert rep.peak_bytes <= 100
+
+
+def test_slot_limit():
+    specs = jobs([0.0] * 6, [1] * 6, iters=2)
+    rep, ex = run(specs, budget=100, max_active=2)
+    assert max(len(ids) for _, ids in ex.steps) == 2
+    assert len(rep.done) == 6
+
+
+def test_job_larger_than_budget_is_rejected():
+    specs = jobs([0.0, 0.0], [500, 10], iters=2)
+    rep, ex = run(specs, budget=100)
+    assert [j.spec["job"] for j in rep.rejected] == [0]
+    assert [j.spec["job"] for j in rep.done] == [1]
+
+
+def test_idle_gap_jumps_to_next_arrival():
+    specs = jobs([0.0, 100.0], [10, 10], iters=1)
+    rep, ex = run(specs, budget=100)
+    assert ex.steps[1][0] == pytest.approx(100.0)
+    lat = sorted(j.latency for j in rep.done)
+    assert lat[0] == pytest.approx(1.25) and lat[1] == pytest.approx(1.25)
+
+
+def test_batching_beats_one_at_a_time_under_load():
+    specs = jobs([0.1 * i for i in range(8)], [10] * 8, iters=5)
+    batched, _ = run(specs, budget=1000)
+    serial, _ = run(specs, budget=1000, max_active=1)
+    assert batched.percentile(50) < serial.percentile(50)
+    assert batched.makespan < serial.makespan
+
+
+def test_poisson_job_stream_is_seeded_and_shaped():
+    a = synth.poisson_jobs(40, rate=2.0)
+    b = synth.poisson_jobs(40, rate=2.0)
+    assert a == b
+    assert a[0]["arrival"] == 0.0
+    assert all(a[i]["arrival"] < a[i + 1]["arrival"] for i in range(39))
+    for s in a:
+        assert s["n"] in (256, 512, 1024) and 180 <= s["n_angles"] <= 1440 and s["ratio"] in (2, 4, 8)
+        assert s["m"] == s["n_angles"] // s["ratio"]
+        assert s["ratio"] * (s["m"] - 1) + s["ratio"] - 1 < s["n_angles"]   # every interleaved subset fits
+    gaps = [a[i + 1]["arrival"] - a[i]["arrival"] for i in range(39)]
+    assert 0.2 < sum(gaps) / len(gaps) < 1.0     # mean gap ~ 1 / rate
+
+
+def test_step_size_is_below_the_curvature_bound():
+    # eta L_MC < 1 for the bound 2 ||A||_1 ||A||_inf with Joseph row/column sums
+    for n, na in ((64, 60), (256, 360), (1024, 1440)):
+        eta = serve.step_size(n, na, 1.0)
+        assert eta * 2 * (1.5 * na) * (2 ** 0.5 * n) < 1.0
