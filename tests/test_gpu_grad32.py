@@ -1,0 +1,95 @@
+"""Gradient of the sketched EI loss with respect to an image batch of 32
+(256 x 256, 360 angles, 363 detectors, a seeded random quarter sketch,
+16 rotations), through the fused step and through the autograd Functions
+(hand-written transposes as backward), against the FP64 oracle's analytic
+gradient -- element by element and along 16 seeded unit directions.
+
+The oracle's own gradient is checked by central differences with h = 1e-4
+along two of the directions.  The loss is an exact quadratic in x, so the
+central difference equals the directional derivative up to FP64 rounding;
+the difference is taken on the oracle only (in FP32 a step of 1e-4 would be
+dominated by cancellation).
+
+Bar: elementwise relerr <= 1e-5 * max(1, kappa) as in the single-image EI
+test (kappa = the gradient's cancellation factor, measured by the oracle);
+directional: |<g - g_oracle, v>| <= 1e-5 * kappa * ||g_oracle||_2 ||v||_2.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import ei_kappa, f32, host, relerr, to_dev
+from paper_2411_05771_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+B, N, NA, ND, C, M = 32, 256, 360, 363, 16, 90
+
+
+def inputs(orc):
+    xt = np.stack([synth.ellipse_phantom(N, synth.SEED_PHANTOM + i) for i in range(B)]).astype(np.float64)
+    yc = orc.radon_fwd(xt, NA, ND)
+    y = f32(np.stack([synth.add_relative_noise(yc[i], synth.std_noise(yc[i].shape, synth.SEED_NOISE + i))
+                      for i in range(B)]))
+    x0 = f32(orc.fbp(y, N, NA))
+    idx = synth.random_sketch(NA, M)
+    cs = f32(synth.cos_sin(synth.rotation_angles(C)))
+    return x0, y, idx, cs
+
+
+def directions(k=16, seed=8000):
+    g = synth.rng(seed)
+    out = []
+    for _ in range(k):
+        v = g.standard_normal((B, N, N))
+        out.append(v / np.linalg.norm(v))
+    return out
+
+
+def test_batch32_gradient_against_oracle(skei, orc):
+    from paper_2411_05771_amd import ei
+    print(f"\n[grad32] B={B} N={N} angles={NA} det={ND} copies={C} m={M}", flush=True)
+    x0, y, idx, cs = inputs(orc)
+    want_l, want_g = orc.ei_loss_grad(x0, y, NA, idx, cs, 1.0)
+    kap = max(ei_kappa(orc, x0[i:i + 1], y[i:i + 1], NA, cs, 1.0, want_g[i:i + 1]) for i in (0, B // 2, B - 1))
+    bar = 1e-5 * max(1.0, kap)
+    print(f"[grad32] oracle loss {want_l:.6e}, kappa ~ {kap:.1f}", flush=True)
+
+    geom = skei.Geometry(N, NA, ND)
+    sk = geom.sketch(idx)
+    step = ei.EIStep(geom, to_dev(y), sk, to_dev(cs), 1.0)
+    loss, g_fused = step(to_dev(x0))
+    g_fused = host(g_fused)
+    x = to_dev(x0).requires_grad_(True)
+    l_auto = ei.ei_loss_autograd(x, to_dev(y), geom, sk, to_dev(cs), 1.0)
+    l_auto.backward()
+    g_auto = host(x.grad)
+
+    e_l = abs(float(loss.item()) - want_l) / abs(want_l)
+    e_f, e_a = relerr(g_fused, want_g), relerr(g_auto, want_g)
+    print(f"[grad32] loss relerr {e_l:.2e}; grad relerr fused {e_f:.2e} autograd {e_a:.2e} (bar {bar:.1e})",
+          flush=True)
+    assert e_l <= 1e-5
+    assert abs(float(l_auto.item()) - want_l) / abs(want_l) <= 1e-5
+    assert e_f <= bar and e_a <= bar
+
+    vs = directions()
+    gn = np.linalg.norm(want_g)
+    worst = 0.0
+    for v in vs:
+        d_or = float(np.vdot(want_g, v))
+        for g in (g_fused, g_auto):
+            worst = max(worst, abs(float(np.vdot(g, v)) - d_or) / gn)
+    print(f"[grad32] worst directional gap / ||g|| = {worst:.2e}", flush=True)
+    assert worst <= bar
+
+    # the oracle's gradient against its own central differences (h = 1e-4)
+    h = 1e-4
+    for v in vs[:2]:
+        lp, _ = orc.ei_loss_grad(x0 + h * v, y, NA, idx, cs, 1.0, want_grad=False)
+        lm, _ = orc.ei_loss_grad(x0 - h * v, y, NA, idx, cs, 1.0, want_grad=False)
+        fd = (lp - lm) / (2 * h)
+        d_or = float(np.vdot(want_g, v))
+        print(f"[grad32] FD {fd:.10e} vs analytic {d_or:.10e}", flush=True)
+        # quadratic loss: only the rounding of the two loss values (~1e-12 of L) over 2h remains
+        assert abs(fd - d_or) <= 1e-6 * abs(d_or) + 1e-12 * (abs(lp) + abs(lm)) / (2 * h)
