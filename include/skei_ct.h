@@ -216,7 +216,7 @@ int skei_ei_plan_run(skei_ei_plan *plan, void *stream);
  *   SKEI_DISPATCH_PERSISTENT: one resident wave of workgroups that draw work
  *     items from per-XCD queues, then steal from the other XCDs' queues;
  *   SKEI_DISPATCH_STATIC: one workgroup per work item, XCD-major ranges.
- * `shape`: rays per thread (1..8) for the ray-driven stages (FWD, BP_T),
+ * `shape`: rays per thread (1..4) for the ray-driven stages (FWD, BP_T),
  * angle groups per pixel (1, 2, 4) for the gathers (BP_RESID, ADJ); 0 keeps
  * the default; ignored by the other stages.  Synchronises the device when
  * the shape changes (the work list is rebuilt). */

@@ -316,12 +316,11 @@ int skei_ei_loss_grad(const skei_geom *g, const float *x, const float *y, int ba
     if (rc) return rc;
 
     const hipStream_t st = S(stream);
-    const int fwd_rpt = std::max(J.fwd_shape[0].rpt, J.fwd_shape[1].rpt);
-    const size_t fwd_shm = std::max(J.fwd_shape[0].shm, J.fwd_shape[1].shm);
+    const RayShape fwd_sh = merge_shapes(J.fwd_shape[0], J.fwd_shape[1]);
     int rpt, block;
     ramp_shape(g->n_det, rpt, block);
     if ((rc = staged(SKEI_STAGE_ROTATE, st, [&] { return rotate_run(inline_jobs(J.rot, 2), st); }))) return rc;
-    if ((rc = staged(SKEI_STAGE_FWD, st, [&] { return ray_run(kRayFwd, false, fwd_rpt, fwd_shm, inline_jobs(J.fwd, 2), st); })))
+    if ((rc = staged(SKEI_STAGE_FWD, st, [&] { return ray_run(kRayFwd, false, fwd_sh, inline_jobs(J.fwd, 2), st); })))
         return rc;
     if ((rc = staged(SKEI_STAGE_RAMP, st,
                      [&] { return ramp_run(false, rpt, block, ramp_shm(g->n_det, false), inline_jobs(&J.ramp, 1), st); })))
@@ -332,7 +331,7 @@ int skei_ei_loss_grad(const skei_geom *g, const float *x, const float *y, int ba
     if ((rc = staged(SKEI_STAGE_REDUCE, st, [&] { return reduce_run(inline_jobs(&J.red, 1), st); }))) return rc;
     if (!grad) return SKEI_OK;
     if ((rc = staged(SKEI_STAGE_BP_T, st,
-                     [&] { return ray_run(kRayBpT, true, J.bpt_shape.rpt, J.bpt_shape.shm, inline_jobs(&J.bpt, 1), st); })))
+                     [&] { return ray_run(kRayBpT, true, J.bpt_shape, inline_jobs(&J.bpt, 1), st); })))
         return rc;
     if ((rc = staged(SKEI_STAGE_RAMP_T, st,
                      [&] { return ramp_run(true, rpt, block, ramp_shm(g->n_det, true), inline_jobs(&J.rampT, 1), st); })))

@@ -40,7 +40,7 @@ typedef __attribute__((address_space(3))) void lmem_t;
 constexpr int kBlock = 256;                  // threads per workgroup (4 waves)
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxG = 8;                     // listed angles per workgroup
-constexpr int kRaysMax = 8 * kBlock;         // rays per workgroup (8 per thread)
+constexpr int kRaysMax = 4 * kBlock;         // rays per workgroup (4 per thread)
 constexpr size_t kLdsBudget = 40 * 1024;     // both staging buffers
 constexpr float kTwoM32 = 2.3283064365386963e-10f;   // 2^-32
 
@@ -64,10 +64,8 @@ int make_ray_job(const skei_geom *g, const float *x, const float *xT, int batch,
     int G;
     if (t.group > 0)
         G = t.group;
-    else if (rpt_cap > 0)
-        G = std::max(1, cap / ((nd + nseg - 1) / nseg));
     else
-        G = base_items >= 2048 ? 4 : base_items >= 1024 ? 2 : 1;
+        G = std::max(1, (rpt_cap > 0 ? cap : 2 * kBlock) / ((nd + nseg - 1) / nseg));
     G = std::max(1, std::min(std::min(G, kMaxG), m));
     for (;;) {
         const int seg = (nd + nseg - 1) / nseg;
@@ -94,10 +92,17 @@ int make_ray_job(const skei_geom *g, const float *x, const float *xT, int batch,
     J.seg = (nd + nseg - 1) / nseg;
     J.ngroups = (m + G - 1) / G;
     J.pitch = line_pitch(n);
-    const int r_lds = (int)(kLdsBudget / (2 * (size_t)J.pitch * sizeof(float)));
-    int R = std::min(std::max(r_lds, 1), std::min(64, n));
+    // lines per unrolled march unit: the largest of 16, 8, 4 whose two
+    // staging buffers fit the LDS budget (4 always fits within 64 KB)
+    const size_t line_bytes = (size_t)J.pitch * sizeof(float);
+    const int U = 2 * 16 * line_bytes <= kLdsBudget ? 16 : 2 * 8 * line_bytes <= kLdsBudget ? 8 : 4;
+    const size_t budget = std::max(kLdsBudget, 2 * (size_t)U * line_bytes);
+    int R = (int)(budget / (2 * line_bytes));
+    R = std::min(R, 64);
     if (t.lines > 0) R = std::min(R, t.lines);
+    R = std::max(U, R / U * U);   // whole units per chunk
     J.R = R;
+    shape.unroll = U;
     J.resid = yfull != nullptr;
     J.items = (long long)batch * J.ngroups * J.nseg;
     shape.rpt = (G * J.seg + kBlock - 1) / kBlock;
@@ -215,6 +220,13 @@ __device__ __forceinline__ void stage_dma(float *buf, int pitch, const float *__
 
 __device__ __forceinline__ void dma_wait() { __builtin_amdgcn_s_waitcnt(0); }
 
+// Zeroes the lines [Rc, R) of a staging buffer: a partial last chunk leaves
+// them unstaged, and whole-unit marches read them (they must add nothing).
+__device__ __forceinline__ void zero_tail(float *buf, int pitch, int R, int Rc)
+{
+    for (int e = Rc * pitch + threadIdx.x; e < R * pitch; e += kBlock) buf[e] = 0.0f;
+}
+
 // ---------------------------------------------------------------------------
 // KIND kFwd: y[b][r][k] = (1/w) sum_M lerp(line_M, u(k, M))       (Joseph A_S)
 //   resid jobs: y = yfull[b][idx[r]][k] - that, in double; partial[item] = sum y^2.
@@ -222,7 +234,7 @@ __device__ __forceinline__ void dma_wait() { __builtin_amdgcn_s_waitcnt(0); }
 //   The pixels within unit distance of the ray in s are the (at most three)
 //   entries within 1/w of u; the four candidates j0-1 .. j0+2 cover them.
 // ---------------------------------------------------------------------------
-template <int KIND, int RPT, typename OUT>
+template <int KIND, int RPT, int U, typename OUT>
 __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float *lds)
 {
     // Lowest tap entry read: j0 for the forward walk, j0 - 1 for B^T; taps
@@ -256,13 +268,13 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
     const float *img = x + (size_t)b * n * n;
     const int buf_stride = R * pitch;
 
-    // Ray slot of (thread, q): blocks of 16 consecutive detectors are dealt
+    // Ray slot of (thread, q): blocks of 32 consecutive detectors are dealt
     // round-robin to the waves, so every wave spans the whole detector range
-    // and marches the same lines (no wave idles at the chunk barriers) while
-    // each 16-lane group reads nearly contiguous LDS entries.
+    // and marches the same lines (no wave idles at the chunk barriers), and
+    // each half-wave reads one contiguous run of LDS entries.
     int rg[RPT], rk[RPT];
     double accd[RPT];
-    const int slot0 = (tid & 15) + 16 * ((tid >> 6) + kWaves * ((tid & 63) >> 4));
+    const int slot0 = (tid & 31) + 32 * ((tid >> 6) + kWaves * ((tid & 63) >> 5));
 #pragma unroll
     for (int q = 0; q < RPT; q++) {
         const int t = slot0 + q * kBlock;
@@ -280,7 +292,7 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
         // Rays of the other branch (and padding rays) are parked far outside
         // the image with a zero step: they read zero borders and add nothing.
         int64_t u[RPT], du[RPT];
-        float facc[RPT], wg[RPT], c1[RPT], c2[RPT];
+        float s0[RPT], s1[RPT], wg[RPT], c1[RPT], c2[RPT];
         int lo = n, hi = -1;
 #pragma unroll
         for (int q = 0; q < RPT; q++) {
@@ -297,7 +309,8 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
             // inside the padded line; one unsigned min clamps both ends
             u[q] = act ? A.base_fx + (int64_t)rk[q] * A.inv_fx + ((int64_t)kBias << 32) : -((int64_t)1 << 44);
             du[q] = act ? A.du_fx : 0;
-            facc[q] = 0.0f;
+            s0[q] = 0.0f;
+            s1[q] = 0.0f;
             wg[q] = A.w * kTwoM32;
             c1[q] = 1.0f - A.w;
             c2[q] = 1.0f - 2.0f * A.w;
@@ -314,20 +327,25 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
             blo = min(blo, wrange[0][w]);
             bhi = max(bhi, wrange[1][w]);
         }
+        // The wave marches whole U-line units, from the unit holding its first
+        // line; on lines outside a ray's own range the ray reads zero borders.
+        const int ulo = lo & ~(U - 1);
 #pragma unroll
-        for (int q = 0; q < RPT; q++) u[q] += (int64_t)lo * du[q];   // position at the wave's first line
+        for (int q = 0; q < RPT; q++) u[q] += (int64_t)ulo * du[q];
 
         const bool rows = pass == 1;
         // column passes read rows of the transposed image when it is given
         const bool dma_rows = rows || xT != nullptr;
         const float *src = rows || !xT ? img : xT + (size_t)b * n * n;
         const int k_last = k_begin + k_len - 1;
+        const unsigned cap = (unsigned)(n + 1 + kBias);
         if (blo <= bhi) {
             const int c_first = blo / R, c_last = bhi / R;
             {
                 const int M0 = c_first * R, Rc = min(R, n - M0);
                 int cl, W;
                 chunk_span(ang, gcount, pass, k_begin, k_last, M0, Rc, n, cl, W);
+                zero_tail(lds, pitch, R, Rc);
                 stage_dma(lds, pitch, src, n, dma_rows, M0, Rc, cl, W);
                 dma_wait();
             }
@@ -339,70 +357,54 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
                     const int M1 = M0 + R, Rc1 = min(R, n - M1);
                     int cl, W;
                     chunk_span(ang, gcount, pass, k_begin, k_last, M1, Rc1, n, cl, W);
-                    stage_dma(lds + (cur ^ 1) * buf_stride, pitch, src, n, dma_rows, M1, Rc1, cl, W);
+                    float *nb = lds + (cur ^ 1) * buf_stride;
+                    zero_tail(nb, pitch, R, Rc1);
+                    stage_dma(nb, pitch, src, n, dma_rows, M1, Rc1, cl, W);
                 }
                 const float *chunk = lds + cur * buf_stride;
-                const int lb = max(lo, M0), le = min(hi, M0 + Rc - 1);
-                if (lb <= le) {
-                    // Software pipeline: the taps of line M+1 are read from LDS
-                    // while line M is accumulated.
-                    constexpr int NT = KIND == kFwd ? 2 : 4;   // taps per line
-                    float ta[RPT][NT], fa[RPT];
-                    auto fetch = [&](int M, float (&t)[RPT][NT], float (&f)[RPT]) {
-                        // entry j of the line sits at index j + kBias of `line`
-                        const float *line = chunk + (M - M0) * pitch + kLinePad - kBias;
+                // units of this chunk that the wave marches (M0 and ulo are multiples of U)
+                const int ub = max(ulo, M0), ue = min(hi, M0 + Rc - 1);
+                for (int Mb = ub; Mb <= ue; Mb += U) {
+                    // entry j of line Mb + l sits at index j + kBias of `line`
+                    const float *ubase = chunk + (Mb - M0) * pitch + kLinePad - kBias;
+#pragma unroll
+                    for (int l = 0; l < U; l++) {
+                        const float *line = ubase + l * pitch;
 #pragma unroll
                         for (int q = 0; q < RPT; q++) {
-                            const unsigned jb = min((unsigned)(int)(u[q] >> 32), (unsigned)(n + 1 + kBias));
-                            f[q] = (float)(uint32_t)u[q];
+                            const unsigned jb = min((unsigned)(int)(u[q] >> 32), cap);
+                            const float fi = (float)(uint32_t)u[q];   // fraction x 2^32
                             u[q] += du[q];
-                            const float *e = line + jb - (KIND == kFwd ? 0 : 1);
-#pragma unroll
-                            for (int t2 = 0; t2 < NT; t2++) t[q][t2] = e[t2];
-                        }
-                    };
-                    // Two register sets alternate (A: even steps, B: odd steps),
-                    // so the pipeline needs no register copies.
-                    auto accumulate = [&](int M, const float (&t)[RPT][NT], const float (&f)[RPT]) {
-#pragma unroll
-                        for (int q = 0; q < RPT; q++) {
                             if constexpr (KIND == kFwd) {
-                                facc[q] += t[q][0];
-                                facc[q] = fmaf(f[q] * kTwoM32, t[q][1] - t[q][0], facc[q]);
+                                const float t0 = line[jb], t1 = line[jb + 1];
+                                s0[q] += t0;
+                                s1[q] = fmaf(fi, t1 - t0, s1[q]);
                             } else {
-                                const float gq = f[q] * wg[q];
+                                const float *e = line + jb - 1;
+                                const float gq = fi * wg[q];
                                 const float wa = fmaxf(c1[q] - gq, 0.0f);   // j0-1: 1 - w (1 + f)
                                 const float wb = 1.0f - gq;                 // j0  : 1 - w f
                                 const float wc = c1[q] + gq;                // j0+1: 1 - w (1 - f)
                                 const float wd = fmaxf(c2[q] + gq, 0.0f);   // j0+2: 1 - w (2 - f)
-                                float ls = wa * t[q][0];
-                                ls = fmaf(wb, t[q][1], ls);
-                                ls = fmaf(wc, t[q][2], ls);
-                                ls = fmaf(wd, t[q][3], ls);
+                                float ls = wa * e[0];
+                                ls = fmaf(wb, e[1], ls);
+                                ls = fmaf(wc, e[2], ls);
+                                ls = fmaf(wd, e[3], ls);
                                 accd[q] += (double)ls;
                             }
                         }
-                        if constexpr (KIND == kFwd) {
-                            // float partial sums over fixed, aligned 16-line blocks: the
-                            // rounding does not depend on chunking, grouping or splits
-                            if ((M & 15) == 15) {
+                    }
+                    if constexpr (KIND == kFwd) {
+                        // float sums over fixed, aligned 16-line blocks: the rounding
+                        // does not depend on chunking, grouping or launch shape
+                        if (((Mb + U) & 15) == 0) {
 #pragma unroll
-                                for (int q = 0; q < RPT; q++) {
-                                    accd[q] += (double)facc[q];
-                                    facc[q] = 0.0f;
-                                }
+                            for (int q = 0; q < RPT; q++) {
+                                accd[q] += fma((double)s1[q], (double)kTwoM32, (double)s0[q]);
+                                s0[q] = 0.0f;
+                                s1[q] = 0.0f;
                             }
                         }
-                    };
-                    float tb[RPT][NT], fb[RPT];
-                    fetch(lb, ta, fa);
-                    for (int M = lb;;) {
-                        if (M + 1 <= le) fetch(M + 1, tb, fb);
-                        accumulate(M, ta, fa);
-                        if (++M > le) break;
-                        if (M + 1 <= le) fetch(M + 1, ta, fa);
-                        accumulate(M, tb, fb);
-                        if (++M > le) break;
                     }
                 }
                 dma_wait();
@@ -414,7 +416,7 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
         }
         if constexpr (KIND == kFwd) {
 #pragma unroll
-            for (int q = 0; q < RPT; q++) accd[q] += (double)facc[q];
+            for (int q = 0; q < RPT; q++) accd[q] += fma((double)s1[q], (double)kTwoM32, (double)s0[q]);
         }
     }
 
@@ -451,60 +453,54 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
     }
 }
 
-template <int KIND, int RPT, typename OUT>
+template <int KIND, int RPT, int U, typename OUT>
 __global__ void __launch_bounds__(kBlock) k_ray(const JobList<RayJob> L)
 {
     extern __shared__ __align__(16) float lds[];
-    for_each_item(L, [&](const RayJob &J, long long item) { ray_item<KIND, RPT, OUT>(J, item, lds); });
+    for_each_item(L, [&](const RayJob &J, long long item) { ray_item<KIND, RPT, U, OUT>(J, item, lds); });
 }
 
-template <int KIND, typename OUT>
-const void *ray_kernel(int rpt)
+template <int KIND, int RPT, int U, typename OUT>
+int ray_launch1(size_t shm, const JobList<RayJob> &L, hipStream_t st)
 {
-    switch (rpt) {
-    case 1: return reinterpret_cast<const void *>(&k_ray<KIND, 1, OUT>);
-    case 2: return reinterpret_cast<const void *>(&k_ray<KIND, 2, OUT>);
-    case 3: return reinterpret_cast<const void *>(&k_ray<KIND, 3, OUT>);
-    case 4: return reinterpret_cast<const void *>(&k_ray<KIND, 4, OUT>);
-    case 5: return reinterpret_cast<const void *>(&k_ray<KIND, 5, OUT>);
-    case 6: return reinterpret_cast<const void *>(&k_ray<KIND, 6, OUT>);
-    case 7: return reinterpret_cast<const void *>(&k_ray<KIND, 7, OUT>);
-    case 8: return reinterpret_cast<const void *>(&k_ray<KIND, 8, OUT>);
-    default: return nullptr;
-    }
-}
-
-template <int KIND, typename OUT>
-int ray_launch(int rpt, size_t shm, const JobList<RayJob> &L, hipStream_t st)
-{
-    const void *kern = ray_kernel<KIND, OUT>(rpt);
-    if (!kern) return SKEI_ERANGE;
-    if (L.total <= 0) return SKEI_OK;
-    const long long grid = launch_grid(L, kern, kBlock, shm);
+    const long long grid = launch_grid(L, reinterpret_cast<const void *>(&k_ray<KIND, RPT, U, OUT>), kBlock, shm);
     if (grid <= 0 || grid > 0x7fffffffLL) return SKEI_ERANGE;
-    switch (rpt) {
-#define SKEI_RAY_CASE(P)                                                                                 \
-    case P: hipLaunchKernelGGL((k_ray<KIND, P, OUT>), dim3((unsigned)grid), dim3(kBlock), shm, st, L); break;
-        SKEI_RAY_CASE(1)
-        SKEI_RAY_CASE(2)
-        SKEI_RAY_CASE(3)
-        SKEI_RAY_CASE(4)
-        SKEI_RAY_CASE(5)
-        SKEI_RAY_CASE(6)
-        SKEI_RAY_CASE(7)
-        SKEI_RAY_CASE(8)
-#undef SKEI_RAY_CASE
-    }
+    hipLaunchKernelGGL((k_ray<KIND, RPT, U, OUT>), dim3((unsigned)grid), dim3(kBlock), shm, st, L);
     return check_launch();
+}
+
+template <int KIND, int U, typename OUT>
+int ray_launch_u(int rpt, size_t shm, const JobList<RayJob> &L, hipStream_t st)
+{
+    switch (rpt) {
+    case 1: return ray_launch1<KIND, 1, U, OUT>(shm, L, st);
+    case 2: return ray_launch1<KIND, 2, U, OUT>(shm, L, st);
+    case 3: return ray_launch1<KIND, 3, U, OUT>(shm, L, st);
+    case 4: return ray_launch1<KIND, 4, U, OUT>(shm, L, st);
+    default: return SKEI_ERANGE;
+    }
+}
+
+template <int KIND, typename OUT>
+int ray_launch(int rpt, int unroll, size_t shm, const JobList<RayJob> &L, hipStream_t st)
+{
+    if (L.total <= 0) return SKEI_OK;
+    switch (unroll) {
+    case 16: return ray_launch_u<KIND, 16, OUT>(rpt, shm, L, st);
+    case 8: return ray_launch_u<KIND, 8, OUT>(rpt, shm, L, st);
+    case 4: return ray_launch_u<KIND, 4, OUT>(rpt, shm, L, st);
+    default: return SKEI_ERANGE;
+    }
 }
 
 }  // namespace
 
-int ray_run(int kind, bool out_double, int rpt, size_t shm, const JobList<RayJob> &L, hipStream_t st)
+int ray_run(int kind, bool out_double, const RayShape &sh, const JobList<RayJob> &L, hipStream_t st)
 {
-    if (shm > 64 * 1024) return SKEI_ERANGE;
-    if (kind == kRayFwd) return out_double ? SKEI_EINVAL : ray_launch<kFwd, float>(rpt, shm, L, st);
-    return out_double ? ray_launch<kBpT, double>(rpt, shm, L, st) : ray_launch<kBpT, float>(rpt, shm, L, st);
+    if (sh.shm > 64 * 1024) return SKEI_ERANGE;
+    if (kind == kRayFwd) return out_double ? SKEI_EINVAL : ray_launch<kFwd, float>(sh.rpt, sh.unroll, sh.shm, L, st);
+    return out_double ? ray_launch<kBpT, double>(sh.rpt, sh.unroll, sh.shm, L, st)
+                      : ray_launch<kBpT, float>(sh.rpt, sh.unroll, sh.shm, L, st);
 }
 
 int launch_radon_fwd(const skei_geom *g, const float *x, const float *xT, int batch, const int32_t *idx, int m,
@@ -514,7 +510,7 @@ int launch_radon_fwd(const skei_geom *g, const float *x, const float *xT, int ba
     RayShape sh;
     int rc = make_ray_job(g, x, xT, batch, idx, m, y, yfull, partial, tune, 0, J, sh);
     if (rc) return rc;
-    return ray_run(kRayFwd, false, sh.rpt, sh.shm, inline_jobs(&J, 1), st);
+    return ray_run(kRayFwd, false, sh, inline_jobs(&J, 1), st);
 }
 
 int launch_bp_T(const skei_geom *g, const float *x, const float *xT, int batch, const int32_t *idx, int m, float *qf,
@@ -524,7 +520,7 @@ int launch_bp_T(const skei_geom *g, const float *x, const float *xT, int batch, 
     RayShape sh;
     int rc = make_ray_job(g, x, xT, batch, idx, m, qd ? (void *)qd : (void *)qf, nullptr, nullptr, tune, 0, J, sh);
     if (rc) return rc;
-    return ray_run(kRayBpT, qd != nullptr, sh.rpt, sh.shm, inline_jobs(&J, 1), st);
+    return ray_run(kRayBpT, qd != nullptr, sh, inline_jobs(&J, 1), st);
 }
 
 }  // namespace skei

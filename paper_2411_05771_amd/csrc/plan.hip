@@ -27,7 +27,6 @@ using namespace skei;
 namespace {
 
 constexpr int kStages = SKEI_STAGE_COUNT;
-constexpr int kDefaultRpt = 3;
 
 struct StageCfg {
     int dispatch = SKEI_DISPATCH_PERSISTENT;
@@ -41,22 +40,14 @@ struct StageTable {
     int chunk = 1;     // persistent draws
     size_t off_jobs = 0, off_first = 0, off_xr = 0;
     // launch parameters
-    int rpt = 0;       // ray stages
-    size_t shm = 0;    // ray / ramp stages
+    RayShape ray{0, 16, 0};   // ray stages
+    size_t shm = 0;           // ramp stages
     int ga = 0;        // gather stages
     int ramp_rpt = 0, ramp_block = 0;
 };
 
 bool is_ray_stage(int s) { return s == SKEI_STAGE_FWD || s == SKEI_STAGE_BP_T; }
 bool is_gather_stage(int s) { return s == SKEI_STAGE_BP_RESID || s == SKEI_STAGE_ADJ; }
-
-// Estimated cost of one item of a job (arbitrary units, only ratios matter).
-double item_cost(const RayJob &j) { return (double)j.G * j.seg * j.n + 4.0 * j.n * j.n / std::max(j.R, 1); }
-double item_cost(const GatherJob &j) { return 256.0 * (j.m + 8); }
-double item_cost(const RampJob &j) { return (double)j.n_det * (j.n_det / 2 + 4); }
-double item_cost(const RotJob &j) { return j.cs ? 256.0 * 4 : 256.0; }
-double item_cost(const RotAdjJob &j) { return 64.0 * 9 * j.copies; }
-double item_cost(const RedJob &j) { return (double)(j.n0 + j.n1); }
 
 // Host image of the device table: appends `bytes` at a 256-byte boundary.
 size_t reserve(std::vector<char> &img, size_t bytes)
@@ -71,35 +62,11 @@ void lay_out(const std::vector<Job> &jobs, StageTable &t, std::vector<char> &img
 {
     t.njobs = (int)jobs.size();
     std::vector<long long> first(jobs.size() + 1, 0);
-    double total_cost = 0.0;
-    for (size_t i = 0; i < jobs.size(); i++) {
-        first[i + 1] = first[i] + jobs[i].items;
-        total_cost += item_cost(jobs[i]) * (double)jobs[i].items;
-    }
+    for (size_t i = 0; i < jobs.size(); i++) first[i + 1] = first[i] + jobs[i].items;
     t.total = first.back();
-    // XCD ranges: cut the item sequence where the running cost first reaches
-    // x/8 of the total (items of a job all cost the same)
-    std::vector<long long> xr(kXcds + 1, t.total);
-    xr[0] = 0;
-    {
-        double run = 0.0;
-        int x = 1;
-        for (size_t i = 0; i < jobs.size() && x < kXcds; i++) {
-            const double c = item_cost(jobs[i]);
-            const long long cnt = jobs[i].items;
-            while (x < kXcds) {
-                const double target = total_cost * x / kXcds;
-                if (run + c * (double)cnt < target) break;
-                long long k = c > 0 ? (long long)std::ceil((target - run) / c) : 0;
-                k = std::max(0LL, std::min(k, cnt));
-                xr[x++] = first[i] + k;
-            }
-            run += c * (double)cnt;
-        }
-        for (int q = 1; q <= kXcds; q++) xr[q] = std::max(xr[q], xr[q - 1]);
-    }
-    long long widest = 0;
-    for (int x = 0; x < kXcds; x++) widest = std::max(widest, xr[x + 1] - xr[x]);
+    std::vector<long long> xr(kXcds + 1);
+    const long long widest = jobs.empty() ? 0 : xcd_ranges(jobs.data(), (int)jobs.size(), first.data(), xr.data());
+    if (jobs.empty()) std::fill(xr.begin(), xr.end(), 0LL);
     t.grid_static = (long long)kXcds * widest;
     // persistent draws: about 16 draws per resident workgroup of an XCD
     // (32 CUs x up to 8 workgroups), at most 64 items per draw
@@ -135,15 +102,21 @@ struct skei_ei_plan {
     bool any_grad = false;
     char *dev = nullptr;
     size_t dev_bytes = 0;
-    WorkQueue *queues = nullptr;   // one per stage, at the start of dev
+    WorkQueue *queues = nullptr;   // two sets per stage, at the start of dev
+    int parity[kStages] = {};      // the set the next launch of a stage uses
 };
 
 namespace {
 
 int plan_build(skei_ei_plan *P)
 {
-    const int fwd_rpt = P->cfg[SKEI_STAGE_FWD].shape > 0 ? P->cfg[SKEI_STAGE_FWD].shape : kDefaultRpt;
-    const int bpt_rpt = P->cfg[SKEI_STAGE_BP_T].shape > 0 ? P->cfg[SKEI_STAGE_BP_T].shape : kDefaultRpt;
+    // default rays per thread: 2 fills a workgroup with one angle of up to
+    // 512 detectors; wider detector rows pack better at 3
+    int max_nd = 1;
+    for (const skei_ei_problem &p : P->probs) max_nd = std::max(max_nd, p.geom->n_det);
+    const int def_rpt = max_nd > 400 ? 3 : 2;
+    const int fwd_rpt = P->cfg[SKEI_STAGE_FWD].shape > 0 ? P->cfg[SKEI_STAGE_FWD].shape : def_rpt;
+    const int bpt_rpt = P->cfg[SKEI_STAGE_BP_T].shape > 0 ? P->cfg[SKEI_STAGE_BP_T].shape : def_rpt;
     std::vector<RotJob> rot;
     std::vector<RayJob> fwd, bpt;
     std::vector<RampJob> ramp, rampT;
@@ -162,8 +135,7 @@ int plan_build(skei_ei_plan *P)
         fwd.push_back(J.fwd[0]);
         fwd.push_back(J.fwd[1]);
         for (int k = 0; k < 2; k++) {
-            t[SKEI_STAGE_FWD].rpt = std::max(t[SKEI_STAGE_FWD].rpt, J.fwd_shape[k].rpt);
-            t[SKEI_STAGE_FWD].shm = std::max(t[SKEI_STAGE_FWD].shm, J.fwd_shape[k].shm);
+            t[SKEI_STAGE_FWD].ray = merge_shapes(t[SKEI_STAGE_FWD].ray, J.fwd_shape[k]);
         }
         ramp.push_back(J.ramp);
         bp.push_back(J.bp);
@@ -171,8 +143,7 @@ int plan_build(skei_ei_plan *P)
         red.push_back(J.red);
         if (J.grad) {
             bpt.push_back(J.bpt);
-            t[SKEI_STAGE_BP_T].rpt = std::max(t[SKEI_STAGE_BP_T].rpt, J.bpt_shape.rpt);
-            t[SKEI_STAGE_BP_T].shm = std::max(t[SKEI_STAGE_BP_T].shm, J.bpt_shape.shm);
+            t[SKEI_STAGE_BP_T].ray = merge_shapes(t[SKEI_STAGE_BP_T].ray, J.bpt_shape);
             rampT.push_back(J.rampT);
             adj.push_back(J.adj[0]);
             adj.push_back(J.adj[1]);
@@ -181,8 +152,6 @@ int plan_build(skei_ei_plan *P)
         }
     }
     // ramp launch shape: rows of up to the widest detector, 256 threads
-    int max_nd = 1;
-    for (const skei_ei_problem &p : P->probs) max_nd = std::max(max_nd, p.geom->n_det);
     for (int s : {SKEI_STAGE_RAMP, SKEI_STAGE_RAMP_T}) {
         t[s].ramp_block = 256;
         t[s].ramp_rpt = (max_nd + 255) / 256;
@@ -193,7 +162,7 @@ int plan_build(skei_ei_plan *P)
     t[SKEI_STAGE_ADJ].ga = gadj > 0 ? gadj : gather_groups_auto(max_m_adj);
 
     std::vector<char> img;
-    reserve(img, sizeof(WorkQueue) * kStages);   // zero cursors
+    reserve(img, sizeof(WorkQueue) * 2 * kStages);   // zero cursors
     lay_out(rot, t[SKEI_STAGE_ROTATE], img);
     lay_out(fwd, t[SKEI_STAGE_FWD], img);
     lay_out(ramp, t[SKEI_STAGE_RAMP], img);
@@ -218,7 +187,10 @@ int plan_build(skei_ei_plan *P)
     }
     if (hipMemcpy(P->dev, img.data(), img.size(), hipMemcpyHostToDevice) != hipSuccess) return SKEI_ELAUNCH;
     P->queues = reinterpret_cast<WorkQueue *>(P->dev);
-    for (int s = 0; s < kStages; s++) P->tab[s] = t[s];
+    for (int s = 0; s < kStages; s++) {
+        P->tab[s] = t[s];
+        P->parity[s] = 0;
+    }
     return SKEI_OK;
 }
 
@@ -231,29 +203,38 @@ JobList<Job> table_list(const skei_ei_plan *P, int s)
     L.jobs = reinterpret_cast<const Job *>(P->dev + t.off_jobs);
     L.first = reinterpret_cast<const long long *>(P->dev + t.off_first);
     L.xr = reinterpret_cast<const long long *>(P->dev + t.off_xr);
-    L.wq = P->cfg[s].dispatch == SKEI_DISPATCH_PERSISTENT ? P->queues + s : nullptr;
+    const bool pers = P->cfg[s].dispatch == SKEI_DISPATCH_PERSISTENT;
+    L.wq = pers ? P->queues + 2 * s + P->parity[s] : nullptr;
+    L.wq_next = pers ? P->queues + 2 * s + (1 - P->parity[s]) : nullptr;
     L.total = t.total;
     L.grid_static = t.grid_static;
     L.chunk = t.chunk;
     return L;
 }
 
-int run_stage(const skei_ei_plan *P, int s, hipStream_t st)
+int launch_stage(const skei_ei_plan *P, int s, hipStream_t st)
 {
     const StageTable &t = P->tab[s];
-    if (t.total <= 0) return SKEI_OK;
     switch (s) {
     case SKEI_STAGE_ROTATE: return rotate_run(table_list<RotJob>(P, s), st);
-    case SKEI_STAGE_FWD: return ray_run(kRayFwd, false, t.rpt, t.shm, table_list<RayJob>(P, s), st);
+    case SKEI_STAGE_FWD: return ray_run(kRayFwd, false, t.ray, table_list<RayJob>(P, s), st);
     case SKEI_STAGE_RAMP: return ramp_run(false, t.ramp_rpt, t.ramp_block, t.shm, table_list<RampJob>(P, s), st);
     case SKEI_STAGE_BP_RESID: return gather_run(kGatherBackproject, t.ga, table_list<GatherJob>(P, s), st);
     case SKEI_STAGE_REDUCE: return reduce_run(table_list<RedJob>(P, s), st);
-    case SKEI_STAGE_BP_T: return ray_run(kRayBpT, true, t.rpt, t.shm, table_list<RayJob>(P, s), st);
+    case SKEI_STAGE_BP_T: return ray_run(kRayBpT, true, t.ray, table_list<RayJob>(P, s), st);
     case SKEI_STAGE_RAMP_T: return ramp_run(true, t.ramp_rpt, t.ramp_block, t.shm, table_list<RampJob>(P, s), st);
     case SKEI_STAGE_ADJ: return gather_run(kGatherJosephAdj, t.ga, table_list<GatherJob>(P, s), st);
     case SKEI_STAGE_ROTATE_ADJ: return rotate_adj_run(table_list<RotAdjJob>(P, s), st);
     default: return SKEI_EINVAL;
     }
+}
+
+int run_stage(skei_ei_plan *P, int s, hipStream_t st)
+{
+    if (P->tab[s].total <= 0) return SKEI_OK;
+    const int rc = launch_stage(P, s, st);
+    if (rc == SKEI_OK && P->cfg[s].dispatch == SKEI_DISPATCH_PERSISTENT) P->parity[s] ^= 1;
+    return rc;
 }
 
 int check_problem(const skei_ei_problem &p)
@@ -419,7 +400,7 @@ int skei_ei_plan_configure(skei_ei_plan *plan, int stage, int dispatch, int shap
 {
     if (!plan || stage < 0 || stage >= kStages) return SKEI_EINVAL;
     if (dispatch != SKEI_DISPATCH_PERSISTENT && dispatch != SKEI_DISPATCH_STATIC) return SKEI_EINVAL;
-    if (is_ray_stage(stage) && (shape < 0 || shape > 8)) return SKEI_EINVAL;
+    if (is_ray_stage(stage) && (shape < 0 || shape > 4)) return SKEI_EINVAL;
     if (is_gather_stage(stage) && !(shape == 0 || shape == 1 || shape == 2 || shape == 4)) return SKEI_EINVAL;
     if (!is_ray_stage(stage) && !is_gather_stage(stage)) shape = 0;
     const bool rebuild = plan->cfg[stage].shape != shape;
@@ -442,7 +423,7 @@ int skei_ei_plan_get_config(const skei_ei_plan *plan, int stage, int *dispatch, 
     if (dispatch) *dispatch = plan->cfg[stage].dispatch;
     if (shape) {
         const StageTable &t = plan->tab[stage];
-        *shape = is_ray_stage(stage) ? t.rpt : is_gather_stage(stage) ? t.ga : 0;
+        *shape = is_ray_stage(stage) ? t.ray.rpt : is_gather_stage(stage) ? t.ga : 0;
     }
     return SKEI_OK;
 }

@@ -135,40 +135,86 @@ struct RedJob {
     long long items;
 };
 
-// Persistent-launch cursors (device memory).  They are zero between launches:
-// the last workgroup to finish a launch resets them.
+// Persistent-launch cursors (device memory), one per XCD range.  A stage
+// alternates between two sets: each launch draws from one and zeroes the
+// other, which the next launch of the stage (stream-ordered after it) uses.
 struct WorkQueue {
     unsigned int next[kXcds];
-    unsigned int done;
-    unsigned int pad_[7];
+    unsigned int pad_[8];
 };
 
 constexpr int kInlineJobs = 2;
 
 // A launch's job list.
 //   inline mode (jobs == nullptr): up to kInlineJobs jobs passed by value;
-//     workgroup L takes item (L % 8) * per + L / 8 of the concatenated items
-//     (XCD-major: each XCD gets one contiguous range).
+//     their concatenated items are cut into 8 contiguous ranges of about
+//     equal cost, and workgroup L takes item L / 8 of range L % 8.
 //   table modes: jobs / first (first global item of each job, njobs + 1
 //     entries) / xr (kXcds + 1 boundaries of the XCD ranges) in device memory.
 //     wq == nullptr: one workgroup per item, XCD x runs its range in order.
-//     wq != nullptr: persistent workgroups draw `chunk` items at a time from
-//     their XCD's queue and then from the other XCDs' queues.
+//     wq != nullptr: persistent workgroups take one item of their XCD's range
+//     each, then draw `chunk` items at a time from their XCD's cursor and
+//     then from the other XCDs' cursors.
 template <typename Job>
 struct JobList {
     Job inl[kInlineJobs];
     long long inl_first[kInlineJobs + 1];
+    long long inl_xr[kXcds + 1];   // inline mode: XCD ranges of the items
     int ninl;
     int njobs;
     const Job *jobs;
     const long long *first;
     const long long *xr;
     WorkQueue *wq;
+    WorkQueue *wq_next;      // zeroed by this launch for the next one
     long long total;
     long long grid_static;   // table mode without queue: 8 * largest XCD range
     int persistent_grid;     // table mode with queue: workgroups to launch (0 = auto)
     int chunk;               // table mode with queue: items per draw (0 = 1)
 };
+
+// Estimated cost of one item of a job (arbitrary units, only ratios matter);
+// used to cut work lists into XCD ranges of about equal cost.
+inline double item_cost(const RayJob &j) { return (double)j.G * j.seg * j.n + 4.0 * j.n * j.n / (j.R > 0 ? j.R : 1); }
+inline double item_cost(const GatherJob &j) { return 256.0 * (j.m + 8); }
+inline double item_cost(const RampJob &j) { return (double)j.n_det * (j.n_det / 2 + 4); }
+inline double item_cost(const RotJob &j) { return j.cs ? 256.0 * 4 : 256.0; }
+inline double item_cost(const RotAdjJob &j) { return 64.0 * 9 * j.copies; }
+inline double item_cost(const RedJob &j) { return (double)(j.n0 + j.n1); }
+
+// Cuts the concatenated items of `count` jobs (first[i] = first item of job
+// i, first[count] = total) where the running cost first reaches x/8 of the
+// total: xr[0..8] with xr[0] = 0 and xr[8] = total.  Returns the largest
+// range.
+template <typename Job>
+inline long long xcd_ranges(const Job *jobs, int count, const long long *first, long long *xr)
+{
+    const long long total = first[count];
+    double total_cost = 0.0;
+    for (int i = 0; i < count; i++) total_cost += item_cost(jobs[i]) * (double)jobs[i].items;
+    for (int x = 0; x <= kXcds; x++) xr[x] = total;
+    xr[0] = 0;
+    double run = 0.0;
+    int x = 1;
+    for (int i = 0; i < count && x < kXcds; i++) {
+        const double c = item_cost(jobs[i]);
+        const long long cnt = jobs[i].items;
+        while (x < kXcds) {
+            const double target = total_cost * x / kXcds;
+            if (run + c * (double)cnt < target) break;
+            long long k = c > 0 ? (long long)((target - run) / c + 0.999999) : 0;
+            k = k < 0 ? 0 : (k > cnt ? cnt : k);
+            xr[x++] = first[i] + k;
+        }
+        run += c * (double)cnt;
+    }
+    long long widest = 0;
+    for (int q = 1; q <= kXcds; q++) {
+        if (xr[q] < xr[q - 1]) xr[q] = xr[q - 1];
+        if (xr[q] - xr[q - 1] > widest) widest = xr[q] - xr[q - 1];
+    }
+    return widest;
+}
 
 template <typename Job>
 inline JobList<Job> inline_jobs(const Job *jobs, int count)
@@ -183,6 +229,7 @@ inline JobList<Job> inline_jobs(const Job *jobs, int count)
     }
     L.inl_first[count] = t;
     L.total = t;
+    L.grid_static = kXcds * xcd_ranges(jobs, count, L.inl_first, L.inl_xr);
     return L;
 }
 
@@ -193,10 +240,27 @@ inline JobList<Job> inline_jobs(const Job *jobs, int count)
 enum RayKind : int { kRayFwd = 0, kRayBpT = 1 };
 enum GatherKind : int { kGatherJosephAdj = 0, kGatherBackproject = 1 };
 
-// Ray kernels: rpt = rays per thread (1..8) >= ceil(G * seg / 256) for every
-// job; shm = LDS bytes >= 2 * R * pitch * 4 for every job; out_double selects
-// the element type of y.
-int ray_run(int kind, bool out_double, int rpt, size_t shm, const JobList<RayJob> &L, hipStream_t st);
+// Launch shape of a ray kernel: rays per thread (1..4), lines per unrolled
+// march unit (16, 8 or 4) and LDS bytes.
+struct RayShape {
+    int rpt;
+    int unroll;
+    size_t shm;
+};
+
+// The shape one launch needs for jobs of shapes a and b.
+inline RayShape merge_shapes(const RayShape &a, const RayShape &b)
+{
+    RayShape r;
+    r.rpt = a.rpt > b.rpt ? a.rpt : b.rpt;
+    r.unroll = a.unroll < b.unroll ? a.unroll : b.unroll;   // units nest: 4 | 8 | 16
+    r.shm = a.shm > b.shm ? a.shm : b.shm;
+    return r;
+}
+
+// Ray kernels: sh.rpt >= ceil(G * seg / 256), sh.shm >= 2 * R * pitch * 4 and
+// R a multiple of sh.unroll for every job; out_double selects y's element type.
+int ray_run(int kind, bool out_double, const RayShape &sh, const JobList<RayJob> &L, hipStream_t st);
 // Gathers with GA angle groups per pixel (1, 2 or 4; results do not depend on it).
 int gather_run(int kind, int ga, const JobList<GatherJob> &L, hipStream_t st);
 // Ramp: rpt >= ceil(n_det / block) for every job, block a multiple of 64,
@@ -214,13 +278,9 @@ struct RayTune {
     int group = 0, lines = 0, split = 0;
 };
 
-// Ray job of one operator application; returns the rays per thread it needs
-// (rpt) and its LDS bytes.  rpt_cap > 0 sizes G and the segments to fill at
-// most rpt_cap * 256 rays per workgroup (tune.group / tune.split still win).
-struct RayShape {
-    int rpt;
-    size_t shm;
-};
+// Ray job of one operator application and the launch shape it needs.
+// rpt_cap > 0 sizes G and the segments to fill at most rpt_cap * 256 rays per
+// workgroup (tune.group / tune.split still win).
 int make_ray_job(const struct ::skei_geom *g, const float *x, const float *xT, int batch, const int32_t *idx,
                  int m, void *y, const float *yfull, double *partial, const RayTune &tune, int rpt_cap,
                  RayJob &job, RayShape &shape);

@@ -56,11 +56,9 @@ template <typename Job, typename Body>
 __device__ __forceinline__ void for_each_item(const JobList<Job> &L, Body &&body)
 {
     if (!L.jobs) {
-        const long long Lb = blockIdx.x;
-        const long long per = (L.total + kXcds - 1) / kXcds;
-        const long long pos = Lb / kXcds;
-        const long long item = (Lb % kXcds) * per + pos;
-        if (pos >= per || item >= L.total) return;
+        const int x = blockIdx.x % kXcds;
+        const long long item = L.inl_xr[x] + blockIdx.x / kXcds;
+        if (item >= L.inl_xr[x + 1]) return;
         if (L.ninl > 1 && item >= L.inl_first[1]) {
             body(L.inl[1], item - L.inl_first[1]);
         } else {
@@ -76,19 +74,35 @@ __device__ __forceinline__ void for_each_item(const JobList<Job> &L, Body &&body
         body(load_job(L.jobs, j), g - load_ll(L.first, j));
         return;
     }
+    // Persistent: workgroup L lives on XCD x0 = L % 8 as the (L / 8)-th of
+    // its XCD's nbx workgroups.  Its first item is the (L / 8)-th of its XCD's
+    // range (no atomic); the rest of every range is handed out `chunk` items
+    // at a time by that XCD's cursor, first to the XCD's own workgroups, then
+    // to any workgroup that has run out of work.
     __shared__ long long s_item;
     const int x0 = blockIdx.x % kXcds;
+    const long long nbx = gridDim.x / kXcds;
     const unsigned chunk = L.chunk > 0 ? (unsigned)L.chunk : 1u;
+    // the cursors of the next launch of this stage start from zero
+    if (blockIdx.x == 0 && threadIdx.x < kXcds)
+        __hip_atomic_store(&L.wq_next->next[threadIdx.x], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    {
+        const long long g = load_ll(L.xr, x0) + blockIdx.x / kXcds;
+        if (g < load_ll(L.xr, x0 + 1)) {
+            const int j = find_job(L.first, L.njobs, g);
+            body(load_job(L.jobs, j), g - load_ll(L.first, j));
+        }
+    }
     for (int q = 0; q < kXcds; q++) {
         const int x = (x0 + q) % kXcds;
-        const long long beg = load_ll(L.xr, x), end = load_ll(L.xr, x + 1);
-        if (beg >= end) continue;
+        const long long beg = load_ll(L.xr, x) + nbx, end = load_ll(L.xr, x + 1);
+        if (beg >= end) continue;   // the static first items covered this range
         const unsigned span = (unsigned)(end - beg);
         for (;;) {
             __syncthreads();   // the previous item is done with s_item and with LDS
             if (threadIdx.x == 0) {
-                // a plain load first: exhausted queues are skipped without a
-                // read-modify-write on their (contended) cursor
+                // a plain load first: exhausted ranges are skipped without a
+                // read-modify-write on their cursor
                 const unsigned seen = __hip_atomic_load(&L.wq->next[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 s_item = seen >= span ? end : beg + (long long)atomicAdd(&L.wq->next[x], chunk);
             }
@@ -97,20 +111,10 @@ __device__ __forceinline__ void for_each_item(const JobList<Job> &L, Body &&body
             if (g0 >= end) break;
             const long long g1 = g0 + chunk < end ? g0 + chunk : end;
             for (long long g = g0; g < g1; g++) {
-                if (g > g0) __syncthreads();
+                __syncthreads();
                 const int j = find_job(L.first, L.njobs, g);
                 body(load_job(L.jobs, j), g - load_ll(L.first, j));
             }
-        }
-    }
-    // Every workgroup has drawn past the end of every queue before it counts
-    // itself done, so the last one can reset the cursors for the next launch.
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        if (atomicAdd(&L.wq->done, 1u) == gridDim.x - 1) {
-            for (int x = 0; x < kXcds; x++) atomicExch(&L.wq->next[x], 0u);
-            atomicExch(&L.wq->done, 0u);
         }
     }
 }
@@ -124,8 +128,7 @@ int resident_workgroups(const void *kernel, int block, size_t shm);
 template <typename Job>
 inline long long launch_grid(const JobList<Job> &L, const void *kernel, int block, size_t shm)
 {
-    if (!L.jobs) return kXcds * ((L.total + kXcds - 1) / kXcds);
-    if (!L.wq) return L.grid_static;
+    if (!L.jobs || !L.wq) return L.grid_static;
     long long grid = L.persistent_grid;
     if (grid <= 0) {
         const int per_device = resident_workgroups(kernel, block, shm);
