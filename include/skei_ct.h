@@ -179,8 +179,9 @@ int skei_ei_loss_grad(const skei_geom *g, const float *x, const float *y, int ba
 /* problems, the dispatch mode or the launch shapes.                    */
 /*                                                                      */
 /* A plan binds the problems' device pointers and a caller workspace of */
-/* skei_ei_plan_workspace_bytes() bytes at creation; it owns a small    */
-/* device table (work lists and queue cursors) that destroy frees.      */
+/* skei_ei_plan_workspace_bytes() bytes (the scratch of every problem   */
+/* that brings none of its own) at creation; it owns a small device     */
+/* table (work lists and queue cursors) that destroy frees.             */
 /* Runs of one plan must not overlap (they share the queue cursors);    */
 /* different plans may run concurrently on different streams.  Problems */
 /* with grad == NULL get the loss only.                                 */
@@ -202,7 +203,14 @@ typedef struct skei_ei_problem {
     float step;                 /* gradient step: after the gradient is  */
                                 /* formed, x -= step * grad (0: x is     */
                                 /* left alone; needs grad)               */
+    void *work;                 /* this problem's own scratch of         */
+    size_t work_bytes;          /* skei_ei_problem_workspace_bytes()     */
+                                /* bytes, or NULL: carved from the plan  */
+                                /* workspace                             */
 } skei_ei_problem;
+
+/* Scratch one problem needs (for skei_ei_problem.work). */
+size_t skei_ei_problem_workspace_bytes(const skei_ei_problem *problem);
 
 typedef struct skei_ei_plan skei_ei_plan;
 

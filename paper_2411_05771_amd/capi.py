@@ -31,7 +31,7 @@ class EiProblem(ctypes.Structure):
         ("geom", c_void_p), ("batch", c_int), ("x", c_void_p), ("y", c_void_p),
         ("mc_idx", c_void_p), ("m_mc", c_int), ("angle_idx", c_void_p), ("m", c_int),
         ("copies", c_int), ("cos_sin", c_void_p), ("lam", c_float), ("loss", c_void_p), ("grad", c_void_p),
-        ("step", c_float),
+        ("step", c_float), ("work", c_void_p), ("work_bytes", c_size_t),
     ]
 
 
@@ -62,6 +62,7 @@ _SIGS = {
     "skei_ei_loss_grad": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_int, c_void_p, c_int,
                                   c_int, c_void_p, c_float, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "skei_ei_plan_workspace_bytes": (c_size_t, [_PROB, c_int]),
+    "skei_ei_problem_workspace_bytes": (c_size_t, [_PROB]),
     "skei_ei_plan_create": (c_int, [_PROB, c_int, c_void_p, c_size_t, ctypes.POINTER(c_void_p)]),
     "skei_ei_plan_destroy": (c_int, [c_void_p]),
     "skei_ei_plan_run": (c_int, [c_void_p, c_void_p]),

@@ -309,21 +309,19 @@ int skei_ei_loss_grad(const skei_geom *g, const float *x, const float *y, int ba
     if ((size_t)batch * copies > 65535) return SKEI_ERANGE;
     EiBuffers b;
     if (!ei_carve(g, batch, m_mc, m, copies, work, work_bytes, b)) return SKEI_ESPACE;
-    const skei_ei_problem p{g, batch, const_cast<float *>(x), y, mc_idx, m_mc, angle_idx, m, copies, cos_sin,
-                            lambda, loss, grad, 0.0f};
+    const skei_ei_problem p{g,      batch, const_cast<float *>(x), y,    mc_idx, m_mc, angle_idx, m, copies, cos_sin,
+                            lambda, loss,  grad,                   0.0f, nullptr, 0};
     EiJobs J;
     int rc = ei_problem_jobs(p, b, 0, 0, J);
     if (rc) return rc;
 
     const hipStream_t st = S(stream);
     const RayShape fwd_sh = merge_shapes(J.fwd_shape[0], J.fwd_shape[1]);
-    int rpt, block;
-    ramp_shape(g->n_det, rpt, block);
     if ((rc = staged(SKEI_STAGE_ROTATE, st, [&] { return rotate_run(inline_jobs(J.rot, 2), st); }))) return rc;
     if ((rc = staged(SKEI_STAGE_FWD, st, [&] { return ray_run(kRayFwd, false, fwd_sh, inline_jobs(J.fwd, 2), st); })))
         return rc;
     if ((rc = staged(SKEI_STAGE_RAMP, st,
-                     [&] { return ramp_run(false, rpt, block, ramp_shm(g->n_det, false), inline_jobs(&J.ramp, 1), st); })))
+                     [&] { return ramp_run(false, ramp_block(g->n_det), ramp_shm(g->n_det), inline_jobs(&J.ramp, 1), st); })))
         return rc;
     if ((rc = staged(SKEI_STAGE_BP_RESID, st,
                      [&] { return gather_run(kGatherBackproject, gather_groups_auto(m), inline_jobs(&J.bp, 1), st); })))
@@ -334,7 +332,7 @@ int skei_ei_loss_grad(const skei_geom *g, const float *x, const float *y, int ba
                      [&] { return ray_run(kRayBpT, true, J.bpt_shape, inline_jobs(&J.bpt, 1), st); })))
         return rc;
     if ((rc = staged(SKEI_STAGE_RAMP_T, st,
-                     [&] { return ramp_run(true, rpt, block, ramp_shm(g->n_det, true), inline_jobs(&J.rampT, 1), st); })))
+                     [&] { return ramp_run(true, ramp_block(g->n_det), ramp_shm(g->n_det), inline_jobs(&J.rampT, 1), st); })))
         return rc;
     if ((rc = staged(SKEI_STAGE_ADJ, st, [&] {
              return gather_run(kGatherJosephAdj, gather_groups_auto(std::max(m, m_mc)), inline_jobs(J.adj, 2), st);

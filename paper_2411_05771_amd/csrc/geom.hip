@@ -99,7 +99,9 @@ int skei_geom_create(int n, int n_angles, int n_det, skei_geom **out)
     }
     // Ram-Lak taps at odd offsets, h(2e+1) = -1/(pi (2e+1))^2; h(0) = 1/4 and
     // the even taps are zero (Kak & Slaney ch. 3, unit detector spacing).
-    const int n_hodd = n_det / 2 + 1;
+    // odd taps h(1), h(3), ... : every offset below N_det, rounded up to a
+    // multiple of 16 taps (the filter kernel steps 4 groups of 4 taps)
+    const int n_hodd = ((n_det / 2 + 1) + 15) / 16 * 16;
     std::vector<double> hodd(n_hodd);
     for (int e = 0; e < n_hodd; e++) {
         const double d = pi * (double)(2 * e + 1);

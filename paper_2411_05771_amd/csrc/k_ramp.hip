@@ -2,103 +2,141 @@
 // ch. 3 with unit detector spacing), as a linear convolution with zero padding.
 //
 // Written in the symmetric form  q[k] = h(0) p[k] + sum_e h(2e+1) (p[k-2e-1] + p[k+2e+1]):
-// the even taps are zero, and the odd taps h(2e+1) = -1/(pi (2e+1))^2 are the
-// same for every lane at a given e (a scalar load), so each lane does two
-// conflict-free LDS reads, one add and one double-precision FMA per pair of
-// taps.  Accumulating in double removes the cancellation error of the
-// high-pass sum (terms of size ~p, result of size ~p/N).
+// the even taps are zero and the odd taps are wave-uniform scalar loads.
+// Each thread owns V consecutive outputs and one of S fixed groups of taps,
+// and keeps two register windows, p[k-d .. k-d+V) and p[k+d .. k+d+V):
+// stepping d by 2 shifts each window by two entries, so a tap costs two new
+// values per side for V outputs.  Accumulation is in double (it removes the
+// cancellation error of the high-pass sum: terms of size ~p, result of size
+// ~p/N), in increasing offset within a group; the S group sums are added in
+// a fixed order.
+#include <algorithm>
+
 #include "skei_internal.h"
 #include "work.h"
 
 namespace skei {
 namespace {
 
-template <int RPT, typename IN>
-__device__ __forceinline__ void ramp_item(const RampJob &J, long long r, IN *row)
+constexpr int kRampV = 8;   // outputs per thread
+constexpr int kRampS = 4;   // tap groups per output (summed in a fixed order)
+
+// Taps stepped per output: every odd offset below N_det, rounded up to whole
+// groups of 4 taps per tap group.  row = [pad | n_det values | pad] in double
+// with pad = 2 E + V + 2, so every window read stays inside the row.
+__device__ __host__ __forceinline__ int ramp_taps(int n_det)
 {
-    // row = [pad | n_det values | pad], pad = n_det + 1
+    const int q = 4 * kRampS;
+    return ((n_det + 1) / 2 + q - 1) / q * q;
+}
+__device__ __host__ __forceinline__ int ramp_pad(int n_det) { return 2 * ramp_taps(n_det) + kRampV + 2; }
+// threads of one tap group: enough for n_det outputs, in whole waves, so that
+// the tap index is uniform across every wave
+__device__ __host__ __forceinline__ int ramp_group(int n_det) { return ((n_det + kRampV - 1) / kRampV + 63) / 64 * 64; }
+
+template <typename IN>
+__device__ __forceinline__ void ramp_item(const RampJob &J, long long r, double *row)
+{
+    constexpr int V = kRampV, S = kRampS;
     const int n_det = J.n_det;
-    const int pad = n_det + 1;
+    const int E = ramp_taps(n_det), ES = E / S;
+    const int pad = ramp_pad(n_det);
     const int tid = threadIdx.x, bs = blockDim.x;
+    const int per = ramp_group(n_det);          // threads per tap group (whole waves)
+    const int len = n_det + 2 * pad;
+    double *part = row + len + (len >> 3) + 1;  // [S - 1][per * V] partial sums
     const IN *src = static_cast<const IN *>(J.p) + (size_t)r * n_det;
-    const double *__restrict__ hodd = J.hodd;
-    for (int e = tid; e < 3 * n_det + 2; e += bs) {
+    // the taps are read-only and wave-uniform: scalar loads
+    typedef __attribute__((address_space(4))) const double ctap_t;
+    const ctap_t *hodd = (const ctap_t *)J.hodd;
+    // Row element q sits at LDS position q + q / 8: a thread's V = 8 outputs
+    // start 9 doubles after its neighbour's, which spreads a wave's reads
+    // over distinct banks.
+    for (int e = tid; e < n_det + 2 * pad; e += bs) {
         const int j = e - pad;
-        row[e] = (j >= 0 && j < n_det) ? src[j] : (IN)0;
+        row[e + (e >> 3)] = (j >= 0 && j < n_det) ? (double)src[j] : 0.0;
     }
     __syncthreads();
 
-    double acc[RPT];
+    // thread (group sg, slot t): outputs k0 .. k0 + V - 1, taps e in [sg ES, (sg + 1) ES)
+    const int sg = tid / per, t = tid - sg * per;
+    const int k0 = t * V;
+    double acc[V];
+    if (sg < S) {
+        // p[k0 + o] for an offset o: element pad + 8 t + o at 9 t + (pad + o) + (pad + o) / 8
+        const double *c = row + 9 * t;
+        auto at = [&](int o) { const int q = pad + o; return c[q + (q >> 3)]; };
+        const int e0 = __builtin_amdgcn_readfirstlane(sg * ES);   // groups are whole waves
+        double L[V], R[V];
 #pragma unroll
-    for (int i = 0; i < RPT; i++) {
-        const int k = tid + i * bs;
-        acc[i] = (k < n_det) ? 0.25 * (double)row[pad + k] : 0.0;
-    }
-    const int E = (n_det + 1) / 2;              // offsets 1, 3, ..., 2E-1 >= n_det - 1
-    for (int e = 0; e < E; e++) {
-        const double h = hodd[e];
-        const int d = 2 * e + 1;
+        for (int i = 0; i < V; i++) {
+            acc[i] = sg == 0 ? 0.25 * at(i) : 0.0;
+            L[i] = at(i - 2 * e0 - 1);   // p[k0 + i - d], d = 2 e0 + 1
+            R[i] = at(i + 2 * e0 + 1);   // p[k0 + i + d]
+        }
+        for (int e = e0; e < e0 + ES; e += 4) {
 #pragma unroll
-        for (int i = 0; i < RPT; i++) {
-            const int k = min(tid + i * bs, n_det - 1);
-            const double pair = (double)row[pad + k - d] + (double)row[pad + k + d];
-            acc[i] = fma(h, pair, acc[i]);
+            for (int u = 0; u < 4; u++) {
+                const double h = hodd[e + u];
+#pragma unroll
+                for (int i = 0; i < V; i++) acc[i] = fma(h, L[i] + R[i], acc[i]);
+                // d -> d + 2: the left window moves two entries down, the right one two up
+                const int d = 2 * (e + u) + 1;
+#pragma unroll
+                for (int i = V - 1; i >= 2; i--) L[i] = L[i - 2];
+                L[1] = at(-d - 1);
+                L[0] = at(-d - 2);
+#pragma unroll
+                for (int i = 0; i < V - 2; i++) R[i] = R[i + 2];
+                R[V - 2] = at(d + V);
+                R[V - 1] = at(d + V + 1);
+            }
+        }
+        if (sg > 0) {
+#pragma unroll
+            for (int i = 0; i < V; i++) part[(sg - 1) * per * V + k0 + i] = acc[i];
         }
     }
+    __syncthreads();
+    if (sg == 0) {
 #pragma unroll
-    for (int i = 0; i < RPT; i++) {
-        const int k = tid + i * bs;
-        if (k < n_det) J.q[(size_t)r * n_det + k] = (float)(acc[i] * (double)J.scale);
+        for (int i = 0; i < V; i++) {
+            const int k = k0 + i;
+            double v = acc[i];
+#pragma unroll
+            for (int g = 1; g < S; g++) v += part[(g - 1) * per * V + k];
+            if (k < n_det) J.q[(size_t)r * n_det + k] = (float)(v * (double)J.scale);
+        }
     }
-}
-
-template <int RPT, typename IN>
-__global__ void __launch_bounds__(256) k_ramp(const JobList<RampJob> L)
-{
-    extern __shared__ __align__(16) unsigned char ramp_raw[];
-    IN *row = reinterpret_cast<IN *>(ramp_raw);
-    for_each_item(L, [&](const RampJob &J, long long r) { ramp_item<RPT, IN>(J, r, row); });
-}
-
-template <int RPT, typename IN>
-int ramp_launch1(int block, size_t shm, const JobList<RampJob> &L, hipStream_t st)
-{
-    const long long grid = launch_grid(L, reinterpret_cast<const void *>(&k_ramp<RPT, IN>), block, shm);
-    if (grid <= 0 || grid > 0x7fffffffLL) return SKEI_ERANGE;
-    hipLaunchKernelGGL((k_ramp<RPT, IN>), dim3((unsigned)grid), dim3(block), shm, st, L);
-    return check_launch();
 }
 
 template <typename IN>
-int ramp_launch(int rpt, int block, size_t shm, const JobList<RampJob> &L, hipStream_t st)
+__global__ void __launch_bounds__(1024) k_ramp(const JobList<RampJob> L)
+{
+    extern __shared__ __align__(16) unsigned char ramp_raw[];
+    double *row = reinterpret_cast<double *>(ramp_raw);
+    for_each_item(L, [&](const RampJob &J, long long r) { ramp_item<IN>(J, r, row); });
+}
+
+template <typename IN>
+int ramp_launch(int block, size_t shm, const JobList<RampJob> &L, hipStream_t st)
 {
     if (L.total <= 0) return SKEI_OK;
-    if (block < 64 || block > 256 || block % 64 || shm > 64 * 1024) return SKEI_ERANGE;
-    switch (rpt) {
-    case 1: return ramp_launch1<1, IN>(block, shm, L, st);
-    case 2: return ramp_launch1<2, IN>(block, shm, L, st);
-    case 3: return ramp_launch1<3, IN>(block, shm, L, st);
-    case 4: return ramp_launch1<4, IN>(block, shm, L, st);
-    case 5: return ramp_launch1<5, IN>(block, shm, L, st);
-    case 6: return ramp_launch1<6, IN>(block, shm, L, st);
-    case 7: return ramp_launch1<7, IN>(block, shm, L, st);
-    case 8: return ramp_launch1<8, IN>(block, shm, L, st);
-    default: return SKEI_ERANGE;
-    }
+    if (block < 64 || block > 1024 || block % 64 || shm > 160 * 1024) return SKEI_ERANGE;
+    const long long grid = launch_grid(L, reinterpret_cast<const void *>(&k_ramp<IN>), block, shm);
+    if (grid <= 0 || grid > 0x7fffffffLL) return SKEI_ERANGE;
+    hipLaunchKernelGGL((k_ramp<IN>), dim3((unsigned)grid), dim3(block), shm, st, L);
+    return check_launch();
 }
 
 }  // namespace
 
-void ramp_shape(int n_det, int &rpt, int &block)
-{
-    rpt = (n_det + 255) / 256;
-    const int per = (n_det + rpt - 1) / rpt;
-    block = ((per + 63) / 64) * 64;
-}
+int ramp_block(int n_det) { return kRampS * ramp_group(n_det); }
 
-size_t ramp_shm(int n_det, bool in_double)
+size_t ramp_shm(int n_det)
 {
-    return (in_double ? sizeof(double) : sizeof(float)) * (size_t)(3 * n_det + 2);
+    const size_t len = (size_t)(n_det + 2 * ramp_pad(n_det));
+    return sizeof(double) * (len + (len >> 3) + 1 + (size_t)(kRampS - 1) * ramp_group(n_det) * kRampV);
 }
 
 RampJob make_ramp_job(const skei_geom *g, const void *p, long long rows, float scale, float *q)
@@ -113,9 +151,9 @@ RampJob make_ramp_job(const skei_geom *g, const void *p, long long rows, float s
     return J;
 }
 
-int ramp_run(bool in_double, int rpt, int block, size_t shm, const JobList<RampJob> &L, hipStream_t st)
+int ramp_run(bool in_double, int block, size_t shm, const JobList<RampJob> &L, hipStream_t st)
 {
-    return in_double ? ramp_launch<double>(rpt, block, shm, L, st) : ramp_launch<float>(rpt, block, shm, L, st);
+    return in_double ? ramp_launch<double>(block, shm, L, st) : ramp_launch<float>(block, shm, L, st);
 }
 
 int launch_ramp(const skei_geom *g, const float *pf, const double *pd, long long rows, float scale, float *q,
@@ -123,9 +161,7 @@ int launch_ramp(const skei_geom *g, const float *pf, const double *pd, long long
 {
     const bool dbl = pd != nullptr;
     const RampJob J = make_ramp_job(g, dbl ? (const void *)pd : (const void *)pf, rows, scale, q);
-    int rpt, block;
-    ramp_shape(g->n_det, rpt, block);
-    return ramp_run(dbl, rpt, block, ramp_shm(g->n_det, dbl), inline_jobs(&J, 1), st);
+    return ramp_run(dbl, ramp_block(g->n_det), ramp_shm(g->n_det), inline_jobs(&J, 1), st);
 }
 
 }  // namespace skei

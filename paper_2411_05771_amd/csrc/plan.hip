@@ -43,7 +43,7 @@ struct StageTable {
     RayShape ray{0, 16, 0};   // ray stages
     size_t shm = 0;           // ramp stages
     int ga = 0;        // gather stages
-    int ramp_rpt = 0, ramp_block = 0;
+    int ramp_block = 0;
 };
 
 bool is_ray_stage(int s) { return s == SKEI_STAGE_FWD || s == SKEI_STAGE_BP_T; }
@@ -153,9 +153,8 @@ int plan_build(skei_ei_plan *P)
     }
     // ramp launch shape: rows of up to the widest detector, 256 threads
     for (int s : {SKEI_STAGE_RAMP, SKEI_STAGE_RAMP_T}) {
-        t[s].ramp_block = 256;
-        t[s].ramp_rpt = (max_nd + 255) / 256;
-        t[s].shm = ramp_shm(max_nd, s == SKEI_STAGE_RAMP_T);
+        t[s].ramp_block = ramp_block(max_nd);
+        t[s].shm = ramp_shm(max_nd);
     }
     const int gbp = P->cfg[SKEI_STAGE_BP_RESID].shape, gadj = P->cfg[SKEI_STAGE_ADJ].shape;
     t[SKEI_STAGE_BP_RESID].ga = gbp > 0 ? gbp : gather_groups_auto(max_m_bp);
@@ -218,11 +217,11 @@ int launch_stage(const skei_ei_plan *P, int s, hipStream_t st)
     switch (s) {
     case SKEI_STAGE_ROTATE: return rotate_run(table_list<RotJob>(P, s), st);
     case SKEI_STAGE_FWD: return ray_run(kRayFwd, false, t.ray, table_list<RayJob>(P, s), st);
-    case SKEI_STAGE_RAMP: return ramp_run(false, t.ramp_rpt, t.ramp_block, t.shm, table_list<RampJob>(P, s), st);
+    case SKEI_STAGE_RAMP: return ramp_run(false, t.ramp_block, t.shm, table_list<RampJob>(P, s), st);
     case SKEI_STAGE_BP_RESID: return gather_run(kGatherBackproject, t.ga, table_list<GatherJob>(P, s), st);
     case SKEI_STAGE_REDUCE: return reduce_run(table_list<RedJob>(P, s), st);
     case SKEI_STAGE_BP_T: return ray_run(kRayBpT, true, t.ray, table_list<RayJob>(P, s), st);
-    case SKEI_STAGE_RAMP_T: return ramp_run(true, t.ramp_rpt, t.ramp_block, t.shm, table_list<RampJob>(P, s), st);
+    case SKEI_STAGE_RAMP_T: return ramp_run(true, t.ramp_block, t.shm, table_list<RampJob>(P, s), st);
     case SKEI_STAGE_ADJ: return gather_run(kGatherJosephAdj, t.ga, table_list<GatherJob>(P, s), st);
     case SKEI_STAGE_ROTATE_ADJ: return rotate_adj_run(table_list<RotAdjJob>(P, s), st);
     default: return SKEI_EINVAL;
@@ -313,6 +312,12 @@ bool cache_find(const std::string &key, StageCfg &cfg)
 
 extern "C" {
 
+size_t skei_ei_problem_workspace_bytes(const skei_ei_problem *p)
+{
+    if (!p || check_problem(*p)) return 0;
+    return align256(ei_workspace_bytes(p->geom, p->batch, p->m_mc, p->m, p->copies));
+}
+
 size_t skei_ei_plan_workspace_bytes(const skei_ei_problem *problems, int count)
 {
     if (!problems || count <= 0) return 0;
@@ -320,7 +325,7 @@ size_t skei_ei_plan_workspace_bytes(const skei_ei_problem *problems, int count)
     for (int i = 0; i < count; i++) {
         const skei_ei_problem &p = problems[i];
         if (check_problem(p)) return 0;
-        total += align256(ei_workspace_bytes(p.geom, p.batch, p.m_mc, p.m, p.copies));
+        if (!p.work) total += skei_ei_problem_workspace_bytes(&p);
     }
     return total;
 }
@@ -328,15 +333,14 @@ size_t skei_ei_plan_workspace_bytes(const skei_ei_problem *problems, int count)
 int skei_ei_plan_create(const skei_ei_problem *problems, int count, void *work, size_t work_bytes,
                         skei_ei_plan **out)
 {
-    if (!problems || count <= 0 || !work || !out) return SKEI_EINVAL;
+    if (!problems || count <= 0 || !out) return SKEI_EINVAL;
     *out = nullptr;
     for (int i = 0; i < count; i++) {
         int rc = check_problem(problems[i]);
         if (rc) return rc;
     }
     const size_t need = skei_ei_plan_workspace_bytes(problems, count);
-    if (need == 0) return SKEI_EINVAL;
-    if (work_bytes < need) return SKEI_ESPACE;
+    if (need > 0 && (!work || work_bytes < need)) return work ? SKEI_ESPACE : SKEI_EINVAL;
     skei_ei_plan *P = new (std::nothrow) skei_ei_plan;
     if (!P) return SKEI_ENOMEM;
     // defaults: long ray-driven items run persistent, short items static
@@ -349,13 +353,15 @@ int skei_ei_plan_create(const skei_ei_problem *problems, int count, void *work, 
     char *w = static_cast<char *>(work);
     for (int i = 0; i < count; i++) {
         const skei_ei_problem &p = problems[i];
-        const size_t b = align256(ei_workspace_bytes(p.geom, p.batch, p.m_mc, p.m, p.copies));
+        const size_t b = skei_ei_problem_workspace_bytes(&p);
         EiBuffers eb;
-        if (!ei_carve(p.geom, p.batch, p.m_mc, p.m, p.copies, w, b, eb)) {
+        const bool own = p.work != nullptr;
+        if ((own && p.work_bytes < b) ||
+            !ei_carve(p.geom, p.batch, p.m_mc, p.m, p.copies, own ? p.work : w, own ? p.work_bytes : b, eb)) {
             delete P;
             return SKEI_ESPACE;
         }
-        w += b;
+        if (!own) w += b;
         P->probs.push_back(p);
         P->bufs.push_back(eb);
         P->any_grad |= p.grad != nullptr;

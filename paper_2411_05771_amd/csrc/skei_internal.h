@@ -263,9 +263,8 @@ inline RayShape merge_shapes(const RayShape &a, const RayShape &b)
 int ray_run(int kind, bool out_double, const RayShape &sh, const JobList<RayJob> &L, hipStream_t st);
 // Gathers with GA angle groups per pixel (1, 2 or 4; results do not depend on it).
 int gather_run(int kind, int ga, const JobList<GatherJob> &L, hipStream_t st);
-// Ramp: rpt >= ceil(n_det / block) for every job, block a multiple of 64,
-// shm >= (3 n_det + 2) * sizeof(element) for every job.
-int ramp_run(bool in_double, int rpt, int block, size_t shm, const JobList<RampJob> &L, hipStream_t st);
+// Ramp: block >= ramp_block(n_det) and shm >= ramp_shm(n_det) for every job.
+int ramp_run(bool in_double, int block, size_t shm, const JobList<RampJob> &L, hipStream_t st);
 int rotate_run(const JobList<RotJob> &L, hipStream_t st);
 int rotate_adj_run(const JobList<RotAdjJob> &L, hipStream_t st);
 int reduce_run(const JobList<RedJob> &L, hipStream_t st);
@@ -293,8 +292,8 @@ size_t gather_items(int n, int batch);
 int gather_groups_auto(int m);   // default GA for m listed angles
 
 RampJob make_ramp_job(const struct ::skei_geom *g, const void *p, long long rows, float scale, float *q);
-void ramp_shape(int n_det, int &rpt, int &block);   // per-row launch shape
-size_t ramp_shm(int n_det, bool in_double);
+int ramp_block(int n_det);      // threads per row
+size_t ramp_shm(int n_det);     // LDS bytes per row
 
 RotJob make_rot_job(const float *x, int batch, int copies, int n, const float *cs, float *out, float *outT);
 RotAdjJob make_rot_adj_job(const float *h, int batch, int copies, int n, const float *cs, float alpha,

@@ -112,7 +112,7 @@ class EIProblem:
     """
 
     def __init__(self, geom: ops.Geometry, x, y, sketch, cos_sin, lam: float = 1.0, mc=None, grad: bool = True,
-                 step: float = 0.0):
+                 step: float = 0.0, own_workspace: bool = False):
         self.geom = geom
         self.x = ops._img(geom, x)
         y3 = y.unsqueeze(0) if y.dim() == 2 else y
@@ -129,13 +129,22 @@ class EIProblem:
         if step and not grad:
             raise ValueError("a gradient step needs the gradient")
         self.step = float(step)   # x -= step * grad after each evaluation (in place)
+        self.work = None          # own scratch (kept across plans), else carved from a plan's workspace
+        if own_workspace:
+            # the size query reads no memory; the loss address is a placeholder
+            nb = int(capi.query("skei_ei_problem_workspace_bytes", ctypes.byref(self.record(256))))
+            if nb == 0:
+                raise ValueError("invalid problem")
+            self.work = torch.empty(nb, dtype=torch.uint8, device=geom.device)
 
     def record(self, loss_ptr: int) -> capi.EiProblem:
         h = self.geom.handle
         return capi.EiProblem(h.value if isinstance(h, ctypes.c_void_p) else h, self.x.shape[0],
                               self.x.data_ptr(), self.y.data_ptr(), self.mc.dev.data_ptr(), self.mc.m,
                               self.sk.dev.data_ptr(), self.sk.m, self.cs.shape[0], self.cs.data_ptr(), self.lam,
-                              loss_ptr, self.grad.data_ptr() if self.grad is not None else None, self.step)
+                              loss_ptr, self.grad.data_ptr() if self.grad is not None else None, self.step,
+                              self.work.data_ptr() if self.work is not None else None,
+                              self.work.numel() if self.work is not None else 0)
 
 
 class EIPlan:
@@ -154,14 +163,13 @@ class EIPlan:
         self.losses = torch.zeros(len(problems), dtype=torch.float64, device=dev)
         base = self.losses.data_ptr()
         self._recs = (capi.EiProblem * len(problems))(*[p.record(base + 8 * i) for i, p in enumerate(problems)])
-        nb = capi.query("skei_ei_plan_workspace_bytes", self._recs, len(problems))
-        if nb == 0:
-            raise ValueError("invalid problem list")
-        self.workspace_bytes = int(nb)
-        self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=dev)
+        self.workspace_bytes = int(capi.query("skei_ei_plan_workspace_bytes", self._recs, len(problems)))
+        self._ws = (torch.empty(self.workspace_bytes, dtype=torch.uint8, device=dev)
+                    if self.workspace_bytes else None)
+        self._dev = dev
         h = ctypes.c_void_p()
-        capi.call("skei_ei_plan_create", self._recs, len(problems), ops._ptr(self._ws), self.workspace_bytes,
-                  ctypes.byref(h))
+        capi.call("skei_ei_plan_create", self._recs, len(problems),
+                  ops._ptr(self._ws) if self._ws is not None else None, self.workspace_bytes, ctypes.byref(h))
         self._h = h
 
     @property
@@ -193,7 +201,7 @@ class EIPlan:
 
     def close(self):
         if self._h is not None:
-            torch.cuda.synchronize(self._ws.device)
+            torch.cuda.synchronize(self._dev)
             capi.call("skei_ei_plan_destroy", self._h)
             self._h = None
 

@@ -24,6 +24,7 @@ logic is tested on the CPU with fakes.
 """
 from __future__ import annotations
 
+import ctypes
 import math
 import time
 from collections import deque
@@ -81,7 +82,8 @@ class ServeReport:
 
 class Server:
     """FIFO admission under a device-memory budget and a slot limit;
-    continuous batching of one iteration of every admitted job per step."""
+    continuous batching: every step advances every admitted job (by one
+    iteration, or by the counts the executor's step returns)."""
 
     def __init__(self, executor, budget_bytes: int, max_active: int = 64, clock=None):
         self.ex = executor
@@ -116,13 +118,13 @@ class Server:
                 if pending:
                     self.clock.sleep_until(pending[0].arrival)
                 continue
-            self.ex.step([j.state for j in active])
+            done_its = self.ex.step([j.state for j in active])
             iters += 1
             sizes.append(len(active))
             now = self.clock.now()
             still = []
-            for j in active:
-                j.it += 1
+            for k, j in enumerate(active):
+                j.it += 1 if done_its is None else int(done_its[k])
                 if j.it >= j.spec["iters"]:
                     j.finished = now
                     j.result = self.ex.finish(j.state)
@@ -143,31 +145,48 @@ def step_size(n: int, n_angles_mc: int, lam: float) -> float:
     return 1.0 / (2.0 * 1.5 * math.sqrt(2.0) * n * n_angles_mc + 20.0 * lam)
 
 
+def iteration_cost(spec) -> float:
+    """Relative device cost of one iteration of a job: ray-lines of its
+    projector work (A on the full scan, A_S on every copy, forward and
+    transpose) -- every operator of the step scales alike."""
+    return float((spec["n_angles"] + spec["copies"] * spec["m"]) * spec["n_det"] * spec["n"])
+
+
 class GpuExecutor:
     """Runs jobs on the device through the library.
 
-    batched=True : one EI plan over all admitted jobs per iteration (rebuilt
-                   only when the set of jobs changes).
+    batched=True : the admitted jobs run as batched EI plans -- one launch per
+                   stage for a whole class of jobs.  With fair=True (default)
+                   jobs are classed by iteration cost and each step gives every
+                   class about the same device time: a job whose iteration
+                   costs 1/k of the most expensive one's runs k iterations
+                   (capped by what it has left), so short jobs are not paced
+                   by long ones.  fair=False runs one iteration of every job
+                   per step in a single plan.
     batched=False: the per-call baseline -- each job has its own one-problem
-                   plan and the jobs' steps run one after another.
+                   plan and the jobs' iterations run one after another, one per
+                   job per step.
+    Each job owns its scratch (allocated at admission and counted in its
+    footprint), so rebuilding a plan allocates only its small work table.
     Inputs (the measured sinograms) are made once by ``prepare`` and kept in
     pinned host memory; ``start`` copies a job's sinogram to the device and
     forms x = FBP(y) there, as a server ingesting a request would.
     """
 
-    def __init__(self, batched: bool = True, lam: float = 1.0, record_loss: bool = False):
+    def __init__(self, batched: bool = True, fair: bool | None = None, lam: float = 1.0,
+                 record_loss: bool = False):
         import torch
 
         from . import ops
         self.torch, self.ops = torch, ops
         self.dev = torch.device("cuda", torch.cuda.current_device())
         self.batched = batched
+        self.fair = batched if fair is None else bool(fair)
         self.lam = float(lam)
         self.record_loss = record_loss
         self.geoms = {}
         self.host_y = {}
-        self._plan = None
-        self._plan_key = None
+        self._plans = {}
         self.plan_builds = 0
 
     # ---------------------------------------------------------------- inputs
@@ -196,9 +215,9 @@ class GpuExecutor:
         g = self.geometry(spec)
         n, na, nd, m, c = spec["n"], spec["n_angles"], spec["n_det"], spec["m"], spec["copies"]
         fake = 256   # sizes only: the query reads no memory
-        rec = (capi.EiProblem * 1)(capi.EiProblem(g.handle.value, 1, fake, fake, fake, na, fake, m, c, fake,
-                                                  self.lam, fake, fake, 0.0))
-        ws = int(capi.query("skei_ei_plan_workspace_bytes", rec, 1))
+        rec = capi.EiProblem(g.handle.value, 1, fake, fake, fake, na, fake, m, c, fake, self.lam, fake, fake, 0.0,
+                             None, 0)
+        ws = int(capi.query("skei_ei_problem_workspace_bytes", ctypes.byref(rec)))
         own = 4 * (3 * n * n + na * nd + spec["ratio"] * m + spec["iters"] * c * 2 + m + 2 * c) + 8 * spec["iters"]
         return ws + own
 
@@ -213,6 +232,7 @@ class GpuExecutor:
         subsets = np.stack([k + ratio * np.arange(m) for k in range(ratio)]).astype(np.int32)
         st = _JobState()
         st.spec = spec
+        st.cost = iteration_cost(spec)
         st.sk_table = torch.from_numpy(subsets).to(self.dev)
         phis = synth.rotation_angles(spec["iters"] * spec["copies"], spec["rotation_seed"])
         st.cs_table = torch.from_numpy(synth.cos_sin(phis).reshape(spec["iters"], spec["copies"], 2)).to(
@@ -221,9 +241,8 @@ class GpuExecutor:
         st.cs = st.cs_table[0].clone()
         st.it = 0
         st.eta = step_size(spec["n"], na, self.lam)
-        st.problem = ei.EIProblem(g, x, y, st.sketch, st.cs, self.lam, grad=True, step=st.eta)
+        st.problem = ei.EIProblem(g, x, y, st.sketch, st.cs, self.lam, grad=True, step=st.eta, own_workspace=True)
         st.loss = torch.zeros(spec["iters"], dtype=torch.float64, device=self.dev) if self.record_loss else None
-        st.own_plan = None if self.batched else ei.EIPlan([st.problem])
         return st
 
     def _inputs(self, st):
@@ -231,42 +250,60 @@ class GpuExecutor:
         st.sketch.dev.copy_(st.sk_table[st.it % st.spec["ratio"]])
         st.cs.copy_(st.cs_table[st.it])
 
-    def step(self, states):
+    def _plan(self, members):
         from . import ei
-        for st in states:
-            self._inputs(st)
+        key = tuple(id(st) for st in members)
+        plan = self._plans.get(key)
+        if plan is None:
+            plan = ei.EIPlan([st.problem for st in members])
+            self._plans[key] = plan
+            self.plan_builds += 1
+        return key, plan
+
+    def _run(self, members, reps):
+        key, plan = self._plan(members)
+        for _ in range(reps):
+            for st in members:
+                self._inputs(st)
+            plan.run()
+            for i, st in enumerate(members):
+                if self.record_loss:
+                    st.loss[st.it].copy_(plan.losses[i])
+                st.it += 1
+        return key
+
+    def step(self, states):
+        """Runs the step; returns the iterations each job advanced."""
+        if self.fair:
+            cmax = max(st.cost for st in states)
+            reps = [max(1, min(int(cmax // st.cost), st.spec["iters"] - st.it)) for st in states]
+        else:
+            reps = [1] * len(states)
+        if any(st.it + r > st.spec["iters"] for st, r in zip(states, reps)):
+            raise RuntimeError("a job was stepped past its iterations")
+        used = set()
         if self.batched:
-            key = tuple(id(st) for st in states)
-            if key != self._plan_key:
-                if self._plan is not None:
-                    self._plan.close()
-                self._plan = ei.EIPlan([st.problem for st in states])
-                self._plan_key = key
-                self.plan_builds += 1
-            self._plan.run()
-            if self.record_loss:
-                for i, st in enumerate(states):
-                    st.loss[st.it].copy_(self._plan.losses[i])
+            classes = {}
+            for st, r in zip(states, reps):
+                classes.setdefault(r, []).append(st)
+            for r in sorted(classes, reverse=True):
+                used.add(self._run(classes[r], r))
         else:
             for st in states:
-                st.own_plan.run()
-                if self.record_loss:
-                    st.loss[st.it].copy_(st.own_plan.losses[0])
-        for st in states:
-            st.it += 1
+                used.add(self._run([st], 1))
+        # plans of classes that no longer exist free their tables
+        for key in [k for k in self._plans if k not in used]:
+            self._plans.pop(key).close()
         self.torch.cuda.synchronize()
+        return reps
 
     def finish(self, st):
-        out = {"x": st.problem.x.clone(), "loss": st.loss}
-        if st.own_plan is not None:
-            st.own_plan.close()
-        return out
+        return {"x": st.problem.x.clone(), "loss": st.loss}
 
     def close(self):
-        if self._plan is not None:
-            self._plan.close()
-            self._plan = None
-            self._plan_key = None
+        for plan in self._plans.values():
+            plan.close()
+        self._plans.clear()
 
 
 class _JobState:

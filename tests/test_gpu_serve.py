@@ -43,8 +43,9 @@ class ClockedExecutor:
         return self.inner.start(spec)
 
     def step(self, states):
-        self.inner.step(states)
+        done = self.inner.step(states)
         self.clock.t += 1.0
+        return done
 
     def finish(self, st):
         return self.inner.finish(st)
@@ -91,6 +92,23 @@ def test_job_results_same_alone_in_mix_and_per_call(skei):
         assert torch.equal(alone.done[0].result["loss"], r["loss"]), f"job {s['job']}: losses differ alone vs mix"
         loss = host(r["loss"])
         assert loss[-1] < loss[0]
+
+
+def test_fair_steps_let_short_jobs_finish_first(skei):
+    big = dict(job=0, arrival=0.0, n=96, n_angles=120, n_det=136, ratio=2, m=60, copies=4, iters=6,
+               phantom_seed=synth.SEED_PHANTOM, rotation_seed=synth.SEED_ROTATION, noise_seed=synth.SEED_NOISE)
+    small = dict(big, job=1, n=32, n_angles=30, n_det=46, m=15, phantom_seed=synth.SEED_PHANTOM + 1)
+    fair, _ = serve_jobs([big, small], batched=True)
+    rr = serve.GpuExecutor(batched=True, fair=False, record_loss=True)
+    rr.prepare([big, small])
+    clock = StepClock()
+    plain = serve.Server(ClockedExecutor(rr, clock), 1 << 34, clock=clock).run([big, small])
+    rr.close()
+    lat = {r: {j.spec["job"]: j.latency for j in rep.done} for r, rep in (("fair", fair), ("rr", plain))}
+    print(f"\n[serve] latency in steps: {lat}", flush=True)
+    assert lat["rr"][1] == 6 and lat["fair"][1] < 6 and lat["fair"][0] == 6
+    for j, k in zip(sorted(fair.done, key=lambda j: j.spec["job"]), sorted(plain.done, key=lambda j: j.spec["job"])):
+        assert torch.equal(j.result["x"], k.result["x"])
 
 
 def test_budget_limits_the_mix(skei):

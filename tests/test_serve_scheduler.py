@@ -145,3 +145,27 @@ def test_step_size_is_below_the_curvature_bound():
     for n, na in ((64, 60), (256, 360), (1024, 1440)):
         eta = serve.step_size(n, na, 1.0)
         assert eta * 2 * (1.5 * na) * (2 ** 0.5 * n) < 1.0
+
+
+class UnevenExecutor(FakeExecutor):
+    """Advances job 0 by two iterations per step (as a fair executor does for
+    a job whose iterations cost half as much)."""
+
+    def step(self, states):
+        super().step(states)
+        return [min(2, s["iters_left"]) if s["job"] == 0 else 1 for s in states]
+
+    def start(self, spec):
+        st = super().start(spec)
+        st["iters_left"] = spec["iters"]
+        return st
+
+
+def test_executor_may_advance_jobs_by_several_iterations():
+    clock = FakeClock()
+    ex = UnevenExecutor(clock, 100)
+    specs = jobs([0.0, 0.0], [10, 10], iters=4)
+    rep = serve.Server(ex, 100, clock=clock).run(specs)
+    steps_of = {j.spec["job"]: sum(j.spec["job"] in ids for _, ids in ex.steps) for j in rep.done}
+    assert steps_of == {0: 2, 1: 4}
+    assert rep.done[0].spec["job"] == 0 and rep.done[0].finished < rep.done[1].finished
