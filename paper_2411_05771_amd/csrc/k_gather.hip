@@ -74,7 +74,7 @@ __device__ __forceinline__ void gather_item(const GatherJob &J, long long item)
         __syncthreads();
         for (int a = tid; a < Ac; a += BS) {
             const AngleRow t = tab[idx[A0 + a]];
-            const double c = t.c, s = t.s;
+            const double c = t.cd, s = t.sd;
             const double X0 = j0 - cN, Y0 = i0 - cN;
             const double org = X0 * c + Y0 * s + cD;
             const double tmin = org + fmin(0.0, (TILE - 1) * c) + fmin(0.0, (TILE - 1) * s);

@@ -23,6 +23,7 @@ struct AngleRow {
     int64_t inv_fx;
     int64_t du_fx;
     double scale;     // 1 / |c_m|   (Joseph step length), double
+    double cd, sd;    // cos theta, sin theta in double (pixel-driven positions)
     float c, s;       // cos theta, sin theta
     float w;          // |c_m| = max(|cos|, |sin|)
     float inv_w2;     // 1 / w^2
@@ -31,7 +32,7 @@ struct AngleRow {
     float inv_m;      // 1 / c_m
     int rows;         // 1: major axis = image rows
 };
-static_assert(sizeof(AngleRow) == 64, "AngleRow layout");
+static_assert(sizeof(AngleRow) == 80, "AngleRow layout");
 
 // LDS line padding used by the ray-driven kernels: every staged image line
 // carries PAD zeros on each side so that clamped tap positions read zeros.

@@ -5,9 +5,10 @@ batch invariance.
 Shapes: the 64^2 / 60-angle / 91-detector plain-operator workload, a ragged
 case (image side not a multiple of 4 or 16, odd angle count so the 45-degree
 tie appears, a sketch with repeats), the 256^2 / 360-angle / 363-detector EI
-workload with 16 rotated copies and a random quarter sketch, and a 1024^2 /
+workload with 16 rotated copies and a random quarter sketch, a 1024^2 /
 1440-angle / 1450-detector image at a 1/8 sketch (several detector passes per
-thread)."""
+thread), the 2 x 2 image, a one-angle sketch, and the largest supported image
+(2032^2) and detector row (2048)."""
 import numpy as np
 import pytest
 
@@ -26,12 +27,20 @@ CASES = {
     "ragged37": (37, 17, 53, 3, "repeats"),
     "ei256_quarter": (256, 360, 363, 16, "random"),
     "big1024_eighth": (1024, 1440, 1450, 1, "eighth"),
+    # degenerate and extreme shapes: the smallest image, a one-angle sketch,
+    # and the largest image and detector the library accepts
+    "tiny2": (2, 4, 3, 2, "full"),
+    "one_angle16": (16, 7, 23, 2, "single"),
+    "max2032": (2032, 8, 2048, 1, "full"),
 }
 
 
 def make_case(name):
     n, na, nd, b, kind = CASES[name]
-    x = np.stack([synth.ellipse_phantom(n, synth.SEED_PHANTOM + i) for i in range(b)]).astype(np.float64)
+    if n < 8:   # too small for the ellipses to cover a pixel centre
+        x = synth.uniform((b, n, n), synth.SEED_PHANTOM)
+    else:
+        x = np.stack([synth.ellipse_phantom(n, synth.SEED_PHANTOM + i) for i in range(b)]).astype(np.float64)
     if kind == "full":
         idx = np.arange(na, dtype=np.int32)
     elif kind == "every4":
@@ -40,6 +49,8 @@ def make_case(name):
         idx = np.array([3, 0, 16, 4, 4, 12, 9, 13], dtype=np.int32)
     elif kind == "random":
         idx = synth.random_sketch(na, na // 4)
+    elif kind == "single":
+        idx = np.array([5], dtype=np.int32)
     else:
         idx = synth.interleaved_sketch(na, 8, 3)
     return n, na, nd, x, idx

@@ -37,7 +37,10 @@ def gpu_problem(skei, ei, p, grad=True, batch=1):
 
 def oracle_problem(skei, ei, orc, p):
     """Problem inputs made by the oracle (for oracle comparisons)."""
-    xt = synth.ellipse_phantom(p["n"], p["phantom_seed"]).astype(np.float64)[None]
+    if p.get("image") == "uniform":     # too small for the ellipses to cover a pixel centre
+        xt = synth.uniform((1, p["n"], p["n"]), p["phantom_seed"])
+    else:
+        xt = synth.ellipse_phantom(p["n"], p["phantom_seed"]).astype(np.float64)[None]
     yc = orc.radon_fwd(xt, p["n_angles"], p["n_det"])
     y = f32(synth.add_relative_noise(yc, synth.std_noise(yc.shape, p["noise_seed"])))
     x0 = f32(orc.fbp(y, p["n"], p["n_angles"]))
@@ -160,4 +163,36 @@ def test_plan_uneven_64_problems(skei, orc):
               f"grad {e_g:.2e} kappa {kap:.1f}", flush=True)
         assert e_l <= 1e-5
         assert e_g <= 1e-5 * max(1.0, kap)
+    plan.close()
+
+
+def test_plan_degenerate_problems(skei, orc):
+    """A 2 x 2 image, one-angle sketches, one copy and a batch of two, mixed
+    with an ordinary problem: bitwise equal to single calls, and at the
+    oracle's values."""
+    from paper_2411_05771_amd import ei
+    base = dict(phantom_seed=synth.SEED_PHANTOM, sketch_seed=synth.SEED_SKETCH,
+                rotation_seed=synth.SEED_ROTATION, noise_seed=synth.SEED_NOISE)
+    specs = [dict(base, n=2, n_angles=4, n_det=3, m=1, copies=1, image="uniform"),
+             dict(base, n=16, n_angles=7, n_det=23, m=1, copies=1),
+             dict(base, n=40, n_angles=90, n_det=58, m=45, copies=2)]
+    probs, inputs = [], []
+    for p in specs:
+        pr, inp = oracle_problem(skei, ei, orc, p)
+        probs.append(pr)
+        inputs.append(inp)
+    refs = [single_call(ei, pr) for pr in probs]
+    plan = ei.EIPlan(probs)
+    for d in (0, 1):
+        for s in ("fwd", "bp_T", "bp_resid", "adj"):
+            plan.configure(s, d, 0)
+        assert_bitwise(plan, refs, f"degenerate, dispatch {d}")
+    for p, pr, (x0, y, idx, cs), (rl, rg) in zip(specs, probs, inputs, refs):
+        wl, wg = orc.ei_loss_grad(x0, y, p["n_angles"], idx, cs, 1.0)
+        kap = ei_kappa(orc, x0, y, p["n_angles"], cs, 1.0, wg)
+        e_l = abs(float(rl.item()) - wl) / abs(wl)
+        e_g = relerr(host(rg), wg)
+        print(f"[plan-degenerate] n={p['n']} m={p['m']} C={p['copies']}: loss {e_l:.2e} grad {e_g:.2e} "
+              f"kappa {kap:.1f}", flush=True)
+        assert e_l <= 1e-5 and e_g <= 1e-5 * max(1.0, kap)
     plan.close()
