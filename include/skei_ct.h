@@ -224,9 +224,10 @@ int skei_ei_plan_run(skei_ei_plan *plan, void *stream);
  *   SKEI_DISPATCH_PERSISTENT: one resident wave of workgroups that draw work
  *     items from per-XCD queues, then steal from the other XCDs' queues;
  *   SKEI_DISPATCH_STATIC: one workgroup per work item, XCD-major ranges.
- * `shape`: rays per thread (1..4) for the ray-driven stages (FWD, BP_T),
- * angle groups per pixel (1, 2, 4) for the gathers (BP_RESID, ADJ); 0 keeps
- * the default; ignored by the other stages.  Synchronises the device when
+ * `shape`: rays per thread (1..4) for the ray-driven stages (FWD, BP_T);
+ * for the gathers (BP_RESID, ADJ) angle groups per pixel (1, 2, 4) with one
+ * pixel per thread, or 10 x groups + 4 (14, 24, 44) with four pixels per
+ * thread; 0 keeps the default; ignored by the other stages.  Synchronises the device when
  * the shape changes (the work list is rebuilt). */
 enum { SKEI_DISPATCH_PERSISTENT = 0, SKEI_DISPATCH_STATIC = 1 };
 int skei_ei_plan_configure(skei_ei_plan *plan, int stage, int dispatch, int shape);

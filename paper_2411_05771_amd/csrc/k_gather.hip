@@ -31,25 +31,29 @@ struct GatherAngle {
     float w, wm1;      // Joseph width max(|cos|,|sin|) and w - 1
 };
 
-// A workgroup holds a 16 x 16 tile x GA angle groups.  The listed angles are
-// split into four fixed classes (r % 4); each class is summed in increasing
-// r, and the four class sums are added in a fixed order.  Thread (pixel, ga)
-// owns the classes ga, ga + GA, ...  Positions are relative to the fixed
-// 16 x 16 tile grid, so every pixel's arithmetic is the same whatever GA, the
-// batch size or the other jobs of the launch -- results are bitwise invariant.
+// A workgroup holds a 16 x 16 tile x GA angle groups; each thread owns PPT
+// pixels of the tile (pixels px, px + 256/PPT, ...), so the per-angle
+// constants and window staging are shared by PPT pixels.  The listed angles
+// are split into four fixed classes (r % 4); each class is summed in
+// increasing r, and the four class sums are added in a fixed order.  Thread
+// (pixel group, ga) owns the classes ga, ga + GA, ...  Positions are relative
+// to the fixed 16 x 16 tile grid, so every pixel's arithmetic is the same
+// whatever GA, PPT, the batch size or the other jobs of the launch -- results
+// are bitwise invariant.
 constexpr int kClasses = 4;
 
-template <int KIND, int GA>
+template <int KIND, int GA, int PPT>
 __device__ __forceinline__ void gather_item(const GatherJob &J, long long item)
 {
-    constexpr int TILE = 16, NPIX = TILE * TILE, BS = NPIX * GA, WIN = 2 * TILE, NC = kClasses / GA;
+    constexpr int TILE = 16, NPIX = TILE * TILE, TPG = NPIX / PPT, BS = TPG * GA, WIN = 2 * TILE;
+    constexpr int NC = kClasses / GA;
     __shared__ GatherAngle prm[kAngleChunk];
     __shared__ int kst[kAngleChunk];                  // first detector of each window
     __shared__ float iw2[kAngleChunk];                // 1/w^2 (Joseph weights)
     __shared__ float2 win[kAngleChunk * WIN];
     __shared__ float part[kClasses][NPIX];
     __shared__ float tileT[TILE][TILE + 1];
-    __shared__ double red[NPIX / 64];
+    __shared__ double pss[NPIX];
     static_assert(kAngleChunk % kClasses == 0, "angle chunks must keep the classes aligned");
 
     const int n = J.n, n_det = J.n_det, m = J.m;
@@ -60,15 +64,22 @@ __device__ __forceinline__ void gather_item(const GatherJob &J, long long item)
     const int b = (int)(item / tiles), tile = (int)(item - (long long)b * tiles);
     const int i0 = (tile / tiles_x) * TILE, j0 = (tile % tiles_x) * TILE;
     const int tid = threadIdx.x;
-    const int px = tid % NPIX, ga = tid / NPIX;
-    const int dx = px % TILE, dy = px / TILE;
-    const double fdx = (double)dx, fdy = (double)dy;
+    const int pg = tid % TPG, ga = tid / TPG;
+    double fdx[PPT], fdy[PPT];
+#pragma unroll
+    for (int v = 0; v < PPT; v++) {
+        const int px = pg + v * TPG;
+        fdx[v] = (double)(px % TILE);
+        fdy[v] = (double)(px / TILE);
+    }
     const double cN = 0.5 * (n - 1), cD = 0.5 * (n_det - 1);
     const float *src = J.in + (size_t)b * m * n_det;
 
-    float acc[NC];
+    float acc[NC][PPT];
 #pragma unroll
-    for (int c = 0; c < NC; c++) acc[c] = 0.0f;
+    for (int c = 0; c < NC; c++)
+#pragma unroll
+        for (int v = 0; v < PPT; v++) acc[c][v] = 0.0f;
     for (int A0 = 0; A0 < m; A0 += kAngleChunk) {
         const int Ac = min(kAngleChunk, m - A0);
         __syncthreads();
@@ -102,79 +113,106 @@ __device__ __forceinline__ void gather_item(const GatherJob &J, long long item)
                 const int a = a4 + ga + c * GA;
                 if (a < Ac) {
                     const GatherAngle p = prm[a];
-                    // window-local detector coordinate in double: exact to ~1e-15 px
-                    const double tl = fma(fdx, p.c, fma(fdy, p.s, p.t0));
-                    const int k0 = (int)tl;                          // 1 <= tl < WIN - 1 by construction
-                    const float f = (float)__builtin_amdgcn_fract(tl);
-                    const float2 e = win[a * WIN + k0];
-                    if (KIND == kJosephAdj) {
-                        // weights Lambda((k - t)/w)/w for k = k0, k0+1 (the 1/w^2 is in the window)
-                        const float wa = fmaxf(p.w - f, 0.0f);
-                        const float wb = fmaxf(f + p.wm1, 0.0f);
-                        acc[c] = fmaf(wa, e.x, acc[c]);
-                        acc[c] = fmaf(wb, e.y, acc[c]);
-                    } else {
-                        acc[c] += e.x;
-                        acc[c] = fmaf(f, e.y, acc[c]);
+                    const float2 *wa_row = win + a * WIN;
+#pragma unroll
+                    for (int v = 0; v < PPT; v++) {
+                        // window-local detector coordinate in double: exact to ~1e-15 px
+                        const double tl = fma(fdx[v], p.c, fma(fdy[v], p.s, p.t0));
+                        const int k0 = (int)tl;                          // 1 <= tl < WIN - 1 by construction
+                        const float f = (float)__builtin_amdgcn_fract(tl);
+                        const float2 e = wa_row[k0];
+                        if (KIND == kJosephAdj) {
+                            // weights Lambda((k - t)/w)/w for k = k0, k0+1 (the 1/w^2 is in the window)
+                            const float wa = fmaxf(p.w - f, 0.0f);
+                            const float wb = fmaxf(f + p.wm1, 0.0f);
+                            acc[c][v] = fmaf(wa, e.x, acc[c][v]);
+                            acc[c][v] = fmaf(wb, e.y, acc[c][v]);
+                        } else {
+                            acc[c][v] += e.x;
+                            acc[c][v] = fmaf(f, e.y, acc[c][v]);
+                        }
                     }
                 }
             }
         }
     }
-    float sum;
+    float sum[PPT];
     if constexpr (GA == 1) {
-        sum = ((acc[0] + acc[1]) + acc[2]) + acc[3];
+#pragma unroll
+        for (int v = 0; v < PPT; v++) sum[v] = ((acc[0][v] + acc[1][v]) + acc[2][v]) + acc[3][v];
     } else {
 #pragma unroll
-        for (int c = 0; c < NC; c++) part[ga + c * GA][px] = acc[c];
+        for (int c = 0; c < NC; c++)
+#pragma unroll
+            for (int v = 0; v < PPT; v++) part[ga + c * GA][pg + v * TPG] = acc[c][v];
         __syncthreads();
-        sum = ((part[0][px] + part[1][px]) + part[2][px]) + part[3][px];
+#pragma unroll
+        for (int v = 0; v < PPT; v++) {
+            const int px = pg + v * TPG;
+            sum[v] = ((part[0][px] + part[1][px]) + part[2][px]) + part[3][px];
+        }
     }
 
     // the threads of angle group 0 write the tile
-    const int i = i0 + dy, j = j0 + dx;
-    double ss = 0.0;
-    float v = 0.0f;
-    if (ga == 0 && i < n && j < n) {
-        const size_t o = ((size_t)b * n + i) * n + j;
-        v = sum * J.scale;
-        if (J.other) {
-            v = J.other[o] - v;
-            ss = (double)v * (double)v;
+    const bool resid = J.other != nullptr;
+#pragma unroll
+    for (int v = 0; v < PPT; v++) {
+        const int px = pg + v * TPG, dx = px % TILE, dy = px / TILE;
+        const int i = i0 + dy, j = j0 + dx;
+        float out = 0.0f;
+        double ss = 0.0;
+        if (ga == 0 && i < n && j < n) {
+            const size_t o = ((size_t)b * n + i) * n + j;
+            out = sum[v] * J.scale;
+            if (resid) {
+                out = J.other[o] - out;
+                ss = (double)out * (double)out;
+            }
+            J.out[o] = out;
         }
-        J.out[o] = v;
+        if (ga == 0) {
+            if (J.outT) tileT[dy][dx] = out;
+            if (resid && J.partial) pss[px] = ss;
+        }
     }
     if (J.outT) {   // the tile again, transposed through LDS (coalesced stores)
-        if (ga == 0) tileT[dy][dx] = v;
         __syncthreads();
-        const int it = j0 + dy, jt = i0 + dx;
-        if (ga == 0 && it < n && jt < n) J.outT[((size_t)b * n + it) * n + jt] = tileT[dx][dy];
+        if (ga == 0) {
+#pragma unroll
+            for (int v = 0; v < PPT; v++) {
+                const int px = pg + v * TPG, dx = px % TILE, dy = px / TILE;
+                const int it = j0 + dy, jt = i0 + dx;
+                if (it < n && jt < n) J.outT[((size_t)b * n + it) * n + jt] = tileT[dx][dy];
+            }
+        }
     }
-    if (J.other && J.partial) {
-        ss = wave_sum(ss);
-        if ((tid & 63) == 0 && tid < NPIX) red[tid >> 6] = ss;
+    if (resid && J.partial) {
+        // per-pixel squares summed in a fixed order, whatever the launch shape:
+        // lane l of the first wave adds pixels l, l + 64, l + 128, l + 192,
+        // then the wave reduces its lanes
         __syncthreads();
-        if (tid == 0) {
-            double s = 0.0;
-            for (int w = 0; w < NPIX / 64; w++) s += red[w];
-            J.partial[item] = s;
+        if (tid < 64) {
+            double s4 = ((pss[tid] + pss[tid + 64]) + pss[tid + 128]) + pss[tid + 192];
+            s4 = wave_sum(s4);
+            if (tid == 0) J.partial[item] = s4;
         }
     }
 }
 
-template <int KIND, int GA>
-__global__ void __launch_bounds__(256 * GA) k_gather(const JobList<GatherJob> L)
+template <int KIND, int GA, int PPT>
+__global__ void __launch_bounds__(256 * GA / PPT) k_gather(const JobList<GatherJob> L)
 {
-    for_each_item(L, [&](const GatherJob &J, long long item) { gather_item<KIND, GA>(J, item); });
+    for_each_item(L, [&](const GatherJob &J, long long item) { gather_item<KIND, GA, PPT>(J, item); });
 }
 
-template <int KIND, int GA>
+template <int KIND, int GA, int PPT>
 int gather_launch(const JobList<GatherJob> &L, hipStream_t st)
 {
     if (L.total <= 0) return SKEI_OK;
-    const long long grid = launch_grid(L, reinterpret_cast<const void *>(&k_gather<KIND, GA>), 256 * GA, 0);
+    constexpr int block = 256 * GA / PPT;
+    const long long grid = launch_grid(L, reinterpret_cast<const void *>(&k_gather<KIND, GA, PPT>), block, 0);
     if (grid <= 0 || grid > 0x7fffffffLL) return SKEI_ERANGE;
-    hipLaunchKernelGGL((k_gather<KIND, GA>), dim3((unsigned)grid), dim3(256 * GA), 0, st, L);
+    hipLaunchKernelGGL((k_gather<KIND, GA, PPT>), dim3((unsigned)grid), dim3(block), 0, st, L);
     return check_launch();
 }
 
@@ -182,9 +220,12 @@ template <int KIND>
 int gather_launch_ga(int ga, const JobList<GatherJob> &L, hipStream_t st)
 {
     switch (ga) {
-    case 1: return gather_launch<KIND, 1>(L, st);
-    case 2: return gather_launch<KIND, 2>(L, st);
-    case 4: return gather_launch<KIND, 4>(L, st);
+    case 1: return gather_launch<KIND, 1, 1>(L, st);
+    case 2: return gather_launch<KIND, 2, 1>(L, st);
+    case 4: return gather_launch<KIND, 4, 1>(L, st);
+    case 14: return gather_launch<KIND, 1, 4>(L, st);
+    case 24: return gather_launch<KIND, 2, 4>(L, st);
+    case 44: return gather_launch<KIND, 4, 4>(L, st);
     default: return SKEI_ERANGE;
     }
 }
@@ -195,7 +236,9 @@ static_assert(2 * 16 >= 2 + 22 + 2, "detector window too small for the pixel til
 
 }  // namespace
 
-int gather_groups_auto(int m) { return m >= 256 ? 2 : 1; }
+// Default gather shape for up to m listed angles: four angle groups with four
+// pixels per thread once there are enough angles to share, else one of each.
+int gather_groups_auto(int m) { return m >= 256 ? 44 : 1; }
 
 size_t gather_items(int n, int batch)
 {

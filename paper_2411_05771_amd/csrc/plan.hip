@@ -37,7 +37,6 @@ struct StageTable {
     int njobs = 0;
     long long total = 0;
     long long grid_static = 0;
-    int chunk = 1;     // persistent draws
     size_t off_jobs = 0, off_first = 0, off_xr = 0;
     // launch parameters
     RayShape ray{0, 16, 0};   // ray stages
@@ -68,9 +67,6 @@ void lay_out(const std::vector<Job> &jobs, StageTable &t, std::vector<char> &img
     const long long widest = jobs.empty() ? 0 : xcd_ranges(jobs.data(), (int)jobs.size(), first.data(), xr.data());
     if (jobs.empty()) std::fill(xr.begin(), xr.end(), 0LL);
     t.grid_static = (long long)kXcds * widest;
-    // persistent draws: about 16 draws per resident workgroup of an XCD
-    // (32 CUs x up to 8 workgroups), at most 64 items per draw
-    t.chunk = (int)std::max(1LL, std::min(64LL, widest / (32LL * 8 * 16)));
     t.off_jobs = reserve(img, sizeof(Job) * std::max<size_t>(jobs.size(), 1));
     if (!jobs.empty()) std::memcpy(img.data() + t.off_jobs, jobs.data(), sizeof(Job) * jobs.size());
     t.off_first = reserve(img, sizeof(long long) * first.size());
@@ -207,7 +203,6 @@ JobList<Job> table_list(const skei_ei_plan *P, int s)
     L.wq_next = pers ? P->queues + 2 * s + (1 - P->parity[s]) : nullptr;
     L.total = t.total;
     L.grid_static = t.grid_static;
-    L.chunk = t.chunk;
     return L;
 }
 
@@ -407,7 +402,9 @@ int skei_ei_plan_configure(skei_ei_plan *plan, int stage, int dispatch, int shap
     if (!plan || stage < 0 || stage >= kStages) return SKEI_EINVAL;
     if (dispatch != SKEI_DISPATCH_PERSISTENT && dispatch != SKEI_DISPATCH_STATIC) return SKEI_EINVAL;
     if (is_ray_stage(stage) && (shape < 0 || shape > 4)) return SKEI_EINVAL;
-    if (is_gather_stage(stage) && !(shape == 0 || shape == 1 || shape == 2 || shape == 4)) return SKEI_EINVAL;
+    if (is_gather_stage(stage) && !(shape == 0 || shape == 1 || shape == 2 || shape == 4 || shape == 14 ||
+                                     shape == 24 || shape == 44))
+        return SKEI_EINVAL;
     if (!is_ray_stage(stage) && !is_gather_stage(stage)) shape = 0;
     const bool rebuild = plan->cfg[stage].shape != shape;
     const StageCfg old = plan->cfg[stage];
@@ -456,7 +453,7 @@ int skei_ei_plan_autotune(skei_ei_plan *plan, void *stream, int reps, const char
         }
         std::vector<int> shapes{0};
         if (is_ray_stage(s)) shapes = {1, 2, 3, 4};
-        if (is_gather_stage(s)) shapes = {1, 2, 4};
+        if (is_gather_stage(s)) shapes = {1, 2, 4, 14, 24, 44};
         float best_ms = 3.0e38f;
         best = plan->cfg[s];
         for (int d : {SKEI_DISPATCH_PERSISTENT, SKEI_DISPATCH_STATIC}) {

@@ -153,9 +153,9 @@ constexpr int kInlineJobs = 2;
 //   table modes: jobs / first (first global item of each job, njobs + 1
 //     entries) / xr (kXcds + 1 boundaries of the XCD ranges) in device memory.
 //     wq == nullptr: one workgroup per item, XCD x runs its range in order.
-//     wq != nullptr: persistent workgroups take one item of their XCD's range
-//     each, then draw `chunk` items at a time from their XCD's cursor and
-//     then from the other XCDs' cursors.
+//     wq != nullptr: persistent workgroups run a static share of their XCD's
+//     range, then draw its remainder and the other XCDs' remainders one item
+//     at a time from per-XCD cursors.
 template <typename Job>
 struct JobList {
     Job inl[kInlineJobs];
@@ -171,7 +171,6 @@ struct JobList {
     long long total;
     long long grid_static;   // table mode without queue: 8 * largest XCD range
     int persistent_grid;     // table mode with queue: workgroups to launch (0 = auto)
-    int chunk;               // table mode with queue: items per draw (0 = 1)
 };
 
 // Estimated cost of one item of a job (arbitrary units, only ratios matter);

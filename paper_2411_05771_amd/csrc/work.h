@@ -74,47 +74,47 @@ __device__ __forceinline__ void for_each_item(const JobList<Job> &L, Body &&body
         body(load_job(L.jobs, j), g - load_ll(L.first, j));
         return;
     }
-    // Persistent: workgroup L lives on XCD x0 = L % 8 as the (L / 8)-th of
-    // its XCD's nbx workgroups.  Its first item is the (L / 8)-th of its XCD's
-    // range (no atomic); the rest of every range is handed out `chunk` items
-    // at a time by that XCD's cursor, first to the XCD's own workgroups, then
-    // to any workgroup that has run out of work.
+    // Persistent: workgroup L lives on XCD x0 = L % 8 as the s-th (s = L / 8)
+    // of its XCD's nbx workgroups.  It first runs its static share of its
+    // XCD's range -- items s, s + nbx, s + 2 nbx, ... of the first
+    // q = floor(span / nbx) * nbx items, no atomics -- then the range's
+    // remainder and, after that, the other XCDs' remainders are handed out
+    // one item per draw by per-XCD cursors.
     __shared__ long long s_item;
     const int x0 = blockIdx.x % kXcds;
-    const long long nbx = gridDim.x / kXcds;
-    const unsigned chunk = L.chunk > 0 ? (unsigned)L.chunk : 1u;
+    const long long nbx = gridDim.x / kXcds, slot = blockIdx.x / kXcds;
     // the cursors of the next launch of this stage start from zero
     if (blockIdx.x == 0 && threadIdx.x < kXcds)
         __hip_atomic_store(&L.wq_next->next[threadIdx.x], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     {
-        const long long g = load_ll(L.xr, x0) + blockIdx.x / kXcds;
-        if (g < load_ll(L.xr, x0 + 1)) {
+        const long long beg = load_ll(L.xr, x0), end = load_ll(L.xr, x0 + 1);
+        const long long q = (end - beg) / nbx;
+        for (long long k = 0; k < q; k++) {
+            if (k > 0) __syncthreads();
+            const long long g = beg + slot + k * nbx;
             const int j = find_job(L.first, L.njobs, g);
             body(load_job(L.jobs, j), g - load_ll(L.first, j));
         }
     }
-    for (int q = 0; q < kXcds; q++) {
-        const int x = (x0 + q) % kXcds;
-        const long long beg = load_ll(L.xr, x) + nbx, end = load_ll(L.xr, x + 1);
-        if (beg >= end) continue;   // the static first items covered this range
+    for (int qx = 0; qx < kXcds; qx++) {
+        const int x = (x0 + qx) % kXcds;
+        const long long xb = load_ll(L.xr, x), end = load_ll(L.xr, x + 1);
+        const long long beg = xb + (end - xb) / nbx * nbx;   // the range's remainder
+        if (beg >= end) continue;
         const unsigned span = (unsigned)(end - beg);
         for (;;) {
             __syncthreads();   // the previous item is done with s_item and with LDS
             if (threadIdx.x == 0) {
-                // a plain load first: exhausted ranges are skipped without a
+                // a plain load first: exhausted remainders are skipped without a
                 // read-modify-write on their cursor
                 const unsigned seen = __hip_atomic_load(&L.wq->next[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                s_item = seen >= span ? end : beg + (long long)atomicAdd(&L.wq->next[x], chunk);
+                s_item = seen >= span ? end : beg + (long long)atomicAdd(&L.wq->next[x], 1u);
             }
             __syncthreads();
-            const long long g0 = uniform64(s_item);
-            if (g0 >= end) break;
-            const long long g1 = g0 + chunk < end ? g0 + chunk : end;
-            for (long long g = g0; g < g1; g++) {
-                __syncthreads();
-                const int j = find_job(L.first, L.njobs, g);
-                body(load_job(L.jobs, j), g - load_ll(L.first, j));
-            }
+            const long long g = uniform64(s_item);
+            if (g >= end) break;
+            const int j = find_job(L.first, L.njobs, g);
+            body(load_job(L.jobs, j), g - load_ll(L.first, j));
         }
     }
 }
