@@ -123,7 +123,8 @@ bool ei_carve(const skei_geom *g, int batch, int m_mc, int m, int copies, void *
     return cv.ok;
 }
 
-int ei_problem_jobs(const skei_ei_problem &p, const EiBuffers &b, int fwd_rpt, int bpt_rpt, EiJobs &J)
+int ei_problem_jobs(const skei_ei_problem &p, const EiBuffers &b, const RayChoice &fwd, const RayChoice &bpt,
+                    EiJobs &J)
 {
     const skei_geom *g = p.geom;
     const int n = g->n, batch = p.batch, copies = p.copies, m = p.m, m_mc = p.m_mc;
@@ -134,7 +135,16 @@ int ei_problem_jobs(const skei_ei_problem &p, const EiBuffers &b, int fwd_rpt, i
     //          r = z - (pi/m) B_S qs ; loss
     J.rot[0] = make_rot_job(p.x, batch, copies, n, p.cos_sin, b.z, b.zT);
     J.rot[1] = make_rot_job(p.x, batch, 1, n, nullptr, nullptr, b.xT);
-    if ((rc = make_ray_job(g, b.z, b.zT, bc, p.angle_idx, m, b.ys, nullptr, nullptr, g->tune_fwd, fwd_rpt, J.fwd[0],
+    RayTune tf = g->tune_fwd, tb = g->tune_bpt;
+    if (!fwd.own) {
+        tf = RayTune{};
+        tf.lines = fwd.lines;
+    }
+    if (!bpt.own) {
+        tb = RayTune{};
+        tb.lines = bpt.lines;
+    }
+    if ((rc = make_ray_job(g, b.z, b.zT, bc, p.angle_idx, m, b.ys, nullptr, nullptr, tf, fwd.rpt, J.fwd[0],
                            J.fwd_shape[0])))
         return rc;
     // The MC residual's sums of squares are per work item, so its items take
@@ -143,6 +153,7 @@ int ei_problem_jobs(const skei_ei_problem &p, const EiBuffers &b, int fwd_rpt, i
     RayTune mc_shape;
     mc_shape.group = 1;
     mc_shape.split = (g->n_det + 511) / 512;
+    mc_shape.lines = tf.lines;   // chunk height does not change the arithmetic
     if ((rc = make_ray_job(g, p.x, b.xT, batch, p.mc_idx, m_mc, b.rmc, p.y, b.pmc, mc_shape, 0, J.fwd[1],
                            J.fwd_shape[1])))
         return rc;
@@ -161,7 +172,7 @@ int ei_problem_jobs(const skei_ei_problem &p, const EiBuffers &b, int fwd_rpt, i
     // backward: ysd = B_S^T r ; qs = (pi/m) H ysd ; z = r - A_S^T qs ;
     //           amc = A_mc^T r_MC ; grad = (2 lambda / C) sum_c T_c^T z - 2 amc
     J.grad = p.grad != nullptr;
-    if ((rc = make_ray_job(g, b.r, b.rT, bc, p.angle_idx, m, b.ysd, nullptr, nullptr, g->tune_bpt, bpt_rpt, J.bpt,
+    if ((rc = make_ray_job(g, b.r, b.rT, bc, p.angle_idx, m, b.ysd, nullptr, nullptr, tb, bpt.rpt, J.bpt,
                            J.bpt_shape)))
         return rc;
     J.rampT = make_ramp_job(g, b.ysd, (long long)bc * m, pim, b.qs);
@@ -312,7 +323,7 @@ int skei_ei_loss_grad(const skei_geom *g, const float *x, const float *y, int ba
     const skei_ei_problem p{g,      batch, const_cast<float *>(x), y,    mc_idx, m_mc, angle_idx, m, copies, cos_sin,
                             lambda, loss,  grad,                   0.0f, nullptr, 0};
     EiJobs J;
-    int rc = ei_problem_jobs(p, b, 0, 0, J);
+    int rc = ei_problem_jobs(p, b, RayChoice{}, RayChoice{}, J);
     if (rc) return rc;
 
     const hipStream_t st = S(stream);

@@ -42,9 +42,15 @@ struct EiJobs {
     bool grad;
 };
 
-// fwd_rpt / bpt_rpt: rays-per-thread caps of the ray jobs (0 = per-problem
-// automatic shape, honouring the geometry's tuning).
-int ei_problem_jobs(const skei_ei_problem &p, const EiBuffers &b, int fwd_rpt, int bpt_rpt, EiJobs &J);
+// Launch shape of a ray stage's jobs: rays-per-thread cap (0 = per-problem
+// automatic shape) and chunk height (0 = the built-in choice).  `own` = use the
+// geometry's tuning (skei_geom_set_tuning) instead.
+struct RayChoice {
+    int rpt = 0, lines = 0;
+    bool own = true;
+};
+int ei_problem_jobs(const skei_ei_problem &p, const EiBuffers &b, const RayChoice &fwd, const RayChoice &bpt,
+                    EiJobs &J);
 
 // Stage probe (skei_probe_set): events around the launch of one stage.
 int probe_begin(int stage, hipStream_t st);

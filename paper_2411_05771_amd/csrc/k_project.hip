@@ -41,7 +41,8 @@ constexpr int kBlock = 256;                  // threads per workgroup (4 waves)
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxG = 8;                     // listed angles per workgroup
 constexpr int kRaysMax = 4 * kBlock;         // rays per workgroup (4 per thread)
-constexpr size_t kLdsBudget = 40 * 1024;     // both staging buffers
+constexpr size_t kLdsBudget = 40 * 1024;     // both staging buffers (default)
+constexpr size_t kLdsMax = 160 * 1024;       // LDS of one CU (gfx950)
 constexpr float kTwoM32 = 2.3283064365386963e-10f;   // 2^-32
 
 enum Kind : int { kFwd = 0, kBpT = 1 };
@@ -95,11 +96,17 @@ int make_ray_job(const skei_geom *g, const float *x, const float *xT, int batch,
     // lines per unrolled march unit: the largest of 16, 8, 4 whose two
     // staging buffers fit the LDS budget (4 always fits within 64 KB)
     const size_t line_bytes = (size_t)J.pitch * sizeof(float);
-    const int U = 2 * 16 * line_bytes <= kLdsBudget ? 16 : 2 * 8 * line_bytes <= kLdsBudget ? 8 : 4;
-    const size_t budget = std::max(kLdsBudget, 2 * (size_t)U * line_bytes);
+    int U = 2 * 16 * line_bytes <= kLdsBudget ? 16 : 2 * 8 * line_bytes <= kLdsBudget ? 8 : 4;
+    size_t budget = std::max(kLdsBudget, 2 * (size_t)U * line_bytes);
+    if (t.lines > 0) {
+        // a requested chunk height sets the unit (16, 8 or 4 lines) and may
+        // spend up to the whole LDS of a CU on the two buffers
+        U = t.lines >= 16 ? 16 : t.lines >= 8 ? 8 : 4;
+        budget = std::min(kLdsMax, std::max(2 * (size_t)U * line_bytes, 2 * (size_t)t.lines * line_bytes));
+        if (2 * (size_t)U * line_bytes > budget) return SKEI_ERANGE;
+    }
     int R = (int)(budget / (2 * line_bytes));
-    R = std::min(R, 64);
-    if (t.lines > 0) R = std::min(R, t.lines);
+    R = std::min(R, t.lines > 0 ? t.lines : 64);
     R = std::max(U, R / U * U);   // whole units per chunk
     J.R = R;
     shape.unroll = U;
@@ -107,7 +114,7 @@ int make_ray_job(const skei_geom *g, const float *x, const float *xT, int batch,
     J.items = (long long)batch * J.ngroups * J.nseg;
     shape.rpt = (G * J.seg + kBlock - 1) / kBlock;
     shape.shm = 2 * (size_t)R * J.pitch * sizeof(float);
-    if (shape.shm > 64 * 1024 || shape.rpt > kRaysMax / kBlock) return SKEI_ERANGE;
+    if (shape.shm > kLdsMax || shape.rpt > kRaysMax / kBlock) return SKEI_ERANGE;
     return SKEI_OK;
 }
 
@@ -497,7 +504,7 @@ int ray_launch(int rpt, int unroll, size_t shm, const JobList<RayJob> &L, hipStr
 
 int ray_run(int kind, bool out_double, const RayShape &sh, const JobList<RayJob> &L, hipStream_t st)
 {
-    if (sh.shm > 64 * 1024) return SKEI_ERANGE;
+    if (sh.shm > kLdsMax) return SKEI_ERANGE;
     if (kind == kRayFwd) return out_double ? SKEI_EINVAL : ray_launch<kFwd, float>(sh.rpt, sh.unroll, sh.shm, L, st);
     return out_double ? ray_launch<kBpT, double>(sh.rpt, sh.unroll, sh.shm, L, st)
                       : ray_launch<kBpT, float>(sh.rpt, sh.unroll, sh.shm, L, st);

@@ -111,8 +111,18 @@ int plan_build(skei_ei_plan *P)
     int max_nd = 1;
     for (const skei_ei_problem &p : P->probs) max_nd = std::max(max_nd, p.geom->n_det);
     const int def_rpt = max_nd > 400 ? 3 : 2;
-    const int fwd_rpt = P->cfg[SKEI_STAGE_FWD].shape > 0 ? P->cfg[SKEI_STAGE_FWD].shape : def_rpt;
-    const int bpt_rpt = P->cfg[SKEI_STAGE_BP_T].shape > 0 ? P->cfg[SKEI_STAGE_BP_T].shape : def_rpt;
+    // ray-stage shape code: rays per thread + 100 x chunk height
+    // (B_S^T, with four taps per line, runs best with the higher occupancy of
+    // 8-line chunks by default)
+    auto choice = [&](int shape, int def_lines) {
+        RayChoice c;
+        c.own = false;
+        c.rpt = shape % 100 > 0 ? shape % 100 : def_rpt;
+        c.lines = shape > 0 ? shape / 100 : def_lines;
+        return c;
+    };
+    const RayChoice fwd_c = choice(P->cfg[SKEI_STAGE_FWD].shape, 0);
+    const RayChoice bpt_c = choice(P->cfg[SKEI_STAGE_BP_T].shape, 8);
     std::vector<RotJob> rot;
     std::vector<RayJob> fwd, bpt;
     std::vector<RampJob> ramp, rampT;
@@ -124,7 +134,7 @@ int plan_build(skei_ei_plan *P)
     for (size_t i = 0; i < P->probs.size(); i++) {
         const skei_ei_problem &p = P->probs[i];
         EiJobs J;
-        int rc = ei_problem_jobs(p, P->bufs[i], fwd_rpt, bpt_rpt, J);
+        int rc = ei_problem_jobs(p, P->bufs[i], fwd_c, bpt_c, J);
         if (rc) return rc;
         rot.push_back(J.rot[0]);
         rot.push_back(J.rot[1]);
@@ -401,7 +411,10 @@ int skei_ei_plan_configure(skei_ei_plan *plan, int stage, int dispatch, int shap
 {
     if (!plan || stage < 0 || stage >= kStages) return SKEI_EINVAL;
     if (dispatch != SKEI_DISPATCH_PERSISTENT && dispatch != SKEI_DISPATCH_STATIC) return SKEI_EINVAL;
-    if (is_ray_stage(stage) && (shape < 0 || shape > 4)) return SKEI_EINVAL;
+    if (is_ray_stage(stage)) {
+        const int rpt = shape % 100, lines = shape / 100;
+        if (shape < 0 || rpt > 4 || !(lines == 0 || lines == 4 || lines == 8 || lines == 16)) return SKEI_EINVAL;
+    }
     if (is_gather_stage(stage) && !(shape == 0 || shape == 1 || shape == 2 || shape == 4 || shape == 14 ||
                                      shape == 24 || shape == 44))
         return SKEI_EINVAL;
@@ -426,7 +439,8 @@ int skei_ei_plan_get_config(const skei_ei_plan *plan, int stage, int *dispatch, 
     if (dispatch) *dispatch = plan->cfg[stage].dispatch;
     if (shape) {
         const StageTable &t = plan->tab[stage];
-        *shape = is_ray_stage(stage) ? t.ray.rpt : is_gather_stage(stage) ? t.ga : 0;
+        *shape = is_ray_stage(stage) ? t.ray.rpt + 100 * (plan->cfg[stage].shape / 100)
+                                     : is_gather_stage(stage) ? t.ga : 0;
     }
     return SKEI_OK;
 }
@@ -452,7 +466,7 @@ int skei_ei_plan_autotune(skei_ei_plan *plan, void *stream, int reps, const char
             continue;
         }
         std::vector<int> shapes{0};
-        if (is_ray_stage(s)) shapes = {1, 2, 3, 4};
+        if (is_ray_stage(s)) shapes = {1, 2, 3, 4, 802, 803, 402, 403};
         if (is_gather_stage(s)) shapes = {1, 2, 4, 14, 24, 44};
         float best_ms = 3.0e38f;
         best = plan->cfg[s];
