@@ -197,31 +197,36 @@ __device__ __forceinline__ void stage_dma(float *buf, int pitch, const float *__
 {
     if (W <= 0) return;
     const int lane = threadIdx.x & 63;
-    // wave-uniform segment bookkeeping lives in scalar registers
+    // wave-uniform bookkeeping lives in scalar registers: wave w stages lines
+    // w, w + 4, ... of the chunk, each in segments of one DMA instruction
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int end = cl + W;
+    float *dst = buf + wave * pitch + kLinePad + cl;
+    const int dst_step = kWaves * pitch;
     if (rows && (n & 3) == 0) {
         const int S = (W + 255) >> 8;
         const int off = 4 * lane;
-        for (int sgi = wave; sgi < Rc * S; sgi += kWaves) {
-            const int l = sgi / S, s = sgi - l * S;
-            const int p0 = cl + (s << 8);
-            const float *src = img + (size_t)(M0 + l) * n + p0;      // uniform
-            if (p0 + off < end)
-                __builtin_amdgcn_global_load_lds((gmem_t *)(src + off), (lmem_t *)(buf + l * pitch + kLinePad + p0),
-                                                 16, 0, 0);
-        }
+        const float *src = img + (size_t)(M0 + wave) * n + cl;
+        const size_t src_step = (size_t)kWaves * n;
+        for (int l = wave; l < Rc; l += kWaves, src += src_step, dst += dst_step)
+            for (int s = 0; s < S; s++) {
+                const int p = s << 8;
+                if (p + off < W)
+                    __builtin_amdgcn_global_load_lds((gmem_t *)(src + p + off), (lmem_t *)(dst + p), 16, 0, 0);
+            }
     } else {
         const int S = (W + 63) >> 6;
+        // rows: entry p of line l at img[(M0 + l) n + p]; columns: at img[p n + M0 + l]
+        const float *src = rows ? img + (size_t)(M0 + wave) * n + cl : img + (size_t)cl * n + M0 + wave;
+        const size_t src_step = rows ? (size_t)kWaves * n : (size_t)kWaves;
         const size_t lane_step = rows ? (size_t)lane : (size_t)lane * n;
-        for (int sgi = wave; sgi < Rc * S; sgi += kWaves) {
-            const int l = sgi / S, s = sgi - l * S;
-            const int p0 = cl + (s << 6);
-            const float *src = rows ? img + (size_t)(M0 + l) * n + p0 : img + (size_t)p0 * n + (M0 + l);   // uniform
-            if (p0 + lane < end)
-                __builtin_amdgcn_global_load_lds((gmem_t *)(src + lane_step), (lmem_t *)(buf + l * pitch + kLinePad + p0),
-                                                 4, 0, 0);
-        }
+        const size_t seg_step = rows ? (size_t)64 : (size_t)64 * n;
+        for (int l = wave; l < Rc; l += kWaves, src += src_step, dst += dst_step)
+            for (int s = 0; s < S; s++) {
+                const int p = s << 6;
+                if (p + lane < W)
+                    __builtin_amdgcn_global_load_lds((gmem_t *)(src + s * seg_step + lane_step), (lmem_t *)(dst + p),
+                                                     4, 0, 0);
+            }
     }
 }
 

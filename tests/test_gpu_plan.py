@@ -196,3 +196,26 @@ def test_plan_degenerate_problems(skei, orc):
               f"kappa {kap:.1f}", flush=True)
         assert e_l <= 1e-5 and e_g <= 1e-5 * max(1.0, kap)
     plan.close()
+
+
+def test_autotuned_ei_workload_plan_matches_oracle(skei, orc):
+    """The EI-step workload (256^2, 360 angles, 363 detectors, 16 copies,
+    random quarter sketch) through an autotuned one-problem plan -- the
+    launch configuration the benchmark times -- against the oracle and,
+    bitwise, against the one-call entry point."""
+    from paper_2411_05771_amd import ei
+    p = dict(n=256, n_angles=360, n_det=363, m=90, copies=16, phantom_seed=synth.SEED_PHANTOM,
+             sketch_seed=synth.SEED_SKETCH, rotation_seed=synth.SEED_ROTATION, noise_seed=synth.SEED_NOISE)
+    pr, (x0, y, idx, cs) = oracle_problem(skei, ei, orc, p)
+    ref = single_call(ei, pr)
+    plan = ei.EIPlan([pr])
+    tuned = plan.autotune(reps=3)
+    print(f"\n[plan-ei256] tuned {tuned}", flush=True)
+    assert_bitwise(plan, [ref], "autotuned EI workload")
+    wl, wg = orc.ei_loss_grad(x0, y, p["n_angles"], idx, cs, 1.0)
+    kap = ei_kappa(orc, x0, y, p["n_angles"], cs, 1.0, wg)
+    e_l = abs(float(plan.losses[0].item()) - wl) / abs(wl)
+    e_g = relerr(host(pr.grad), wg)
+    print(f"[plan-ei256] loss {e_l:.2e} grad {e_g:.2e} kappa {kap:.1f}", flush=True)
+    assert e_l <= 1e-5 and e_g <= 1e-5 * max(1.0, kap)
+    plan.close()
