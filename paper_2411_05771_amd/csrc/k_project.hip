@@ -274,8 +274,16 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
     const int k_begin = sg * seg, k_len = min(seg, n_det - k_begin);
     const int tid = threadIdx.x;
     if (tid < gcount) ang[tid] = tab[idx[r0 + tid]];
-    // zero both buffers once: the DMA only ever writes inside [0, n) of a line
-    for (int e = tid; e < 2 * R * pitch; e += kBlock) lds[e] = 0.0f;
+    // Zero the pads of every line of both buffers: the DMA never writes them,
+    // and clamped taps read them.  Entries of [0, n) outside a chunk's staged
+    // span are never read (the span covers every tap of the group's rays).
+    {
+        const int padw = pitch - n;   // kLinePad before the line, the rest after it
+        for (int e = tid; e < 2 * R * padw; e += kBlock) {
+            const int l = e / padw, k = e - l * padw;
+            lds[l * pitch + (k < kLinePad ? k : n + k)] = 0.0f;
+        }
+    }
     __syncthreads();
     const float *img = x + (size_t)b * n * n;
     const int buf_stride = R * pitch;
