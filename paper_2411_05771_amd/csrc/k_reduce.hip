@@ -8,7 +8,7 @@
 namespace skei {
 namespace {
 
-constexpr int kRedBlock = 256;
+constexpr int kRedBlock = 1024;
 constexpr size_t kRedChunk = 4096;   // elements per partial
 
 __device__ __forceinline__ double block_sum(double v, double *sh)

@@ -40,9 +40,12 @@ __device__ __forceinline__ Sample sample_point(int i, int j, float c, float s, d
     return r;
 }
 
-// One 16 x 16 output tile per work item; the tile is also written transposed
-// (through LDS, so both stores are coalesced) when outT is given.  Jobs
-// without rotations (cs == nullptr) copy / transpose the image exactly.
+// One 16 x 16 output tile per work item, 64 threads, four rows of the tile
+// per thread (more loads in flight per thread); the tile is also written
+// transposed (through LDS, so both stores are coalesced) when outT is given.
+// Jobs without rotations (cs == nullptr) copy / transpose the image exactly.
+constexpr int kRotThreads = 64;
+
 __device__ __forceinline__ void rotate_item(const RotJob &J, long long item)
 {
     __shared__ float tile[16][17];
@@ -54,40 +57,51 @@ __device__ __forceinline__ void rotate_item(const RotJob &J, long long item)
     const int i0 = (t / tiles_x) * 16, j0 = (t % tiles_x) * 16;
     const long long b = bc / copies;
     const int c = (int)(bc - b * copies);
-    const int dx = threadIdx.x & 15, dy = threadIdx.x >> 4;
-    const int i = i0 + dy, j = j0 + dx;
+    const int dx = threadIdx.x & 15, dy0 = threadIdx.x >> 4;   // rows dy0, dy0 + 4, dy0 + 8, dy0 + 12
     const float *img = J.x + (size_t)b * n * n;
-    float acc = 0.0f;
-    if (i < n && j < n) {
-        if (J.cs) {
-            const double cN = 0.5 * (double)(n - 1);
-            const Sample sp = sample_point(i, j, J.cs[2 * c], J.cs[2 * c + 1], cN);
+    const double cN = 0.5 * (double)(n - 1);
+    const float co = J.cs ? J.cs[2 * c] : 1.0f, si = J.cs ? J.cs[2 * c + 1] : 0.0f;
+    float acc[4];
 #pragma unroll
-            for (int di = 0; di < 2; di++) {
-                const int ii = sp.i0 + di;
-                const float wv = di ? sp.av : 1.0f - sp.av;
+    for (int r = 0; r < 4; r++) {
+        const int dy = dy0 + 4 * r, i = i0 + dy, j = j0 + dx;
+        float a = 0.0f;
+        if (i < n && j < n) {
+            if (J.cs) {
+                const Sample sp = sample_point(i, j, co, si, cN);
 #pragma unroll
-                for (int dj = 0; dj < 2; dj++) {
-                    const int jj = sp.j0 + dj;
-                    const float wu = dj ? sp.au : 1.0f - sp.au;
-                    if (ii >= 0 && ii < n && jj >= 0 && jj < n) acc = fmaf(wv * wu, img[(size_t)ii * n + jj], acc);
+                for (int di = 0; di < 2; di++) {
+                    const int ii = sp.i0 + di;
+                    const float wv = di ? sp.av : 1.0f - sp.av;
+#pragma unroll
+                    for (int dj = 0; dj < 2; dj++) {
+                        const int jj = sp.j0 + dj;
+                        const float wu = dj ? sp.au : 1.0f - sp.au;
+                        if (ii >= 0 && ii < n && jj >= 0 && jj < n) a = fmaf(wv * wu, img[(size_t)ii * n + jj], a);
+                    }
                 }
+            } else {
+                a = img[(size_t)i * n + j];
             }
-        } else {
-            acc = img[(size_t)i * n + j];
+            if (J.out) J.out[(size_t)bc * n * n + (size_t)i * n + j] = a;
         }
-        if (J.out) J.out[(size_t)bc * n * n + (size_t)i * n + j] = acc;
+        acc[r] = a;
     }
     if (J.outT) {
         __syncthreads();   // an earlier item of this workgroup may still read the tile
-        tile[dy][dx] = acc;
+#pragma unroll
+        for (int r = 0; r < 4; r++) tile[dy0 + 4 * r][dx] = acc[r];
         __syncthreads();
-        const int it = j0 + dy, jt = i0 + dx;   // transposed position: row = original column
-        if (it < n && jt < n) J.outT[(size_t)bc * n * n + (size_t)it * n + jt] = tile[dx][dy];
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int dy = dy0 + 4 * r;
+            const int it = j0 + dy, jt = i0 + dx;   // transposed position: row = original column
+            if (it < n && jt < n) J.outT[(size_t)bc * n * n + (size_t)it * n + jt] = tile[dx][dy];
+        }
     }
 }
 
-__global__ void __launch_bounds__(256) k_rotate(const JobList<RotJob> L)
+__global__ void __launch_bounds__(kRotThreads) k_rotate(const JobList<RotJob> L)
 {
     for_each_item(L, [&](const RotJob &J, long long item) { rotate_item(J, item); });
 }
@@ -190,9 +204,9 @@ RotAdjJob make_rot_adj_job(const float *h, int batch, int copies, int n, const f
 int rotate_run(const JobList<RotJob> &L, hipStream_t st)
 {
     if (L.total <= 0) return SKEI_OK;
-    const long long grid = launch_grid(L, reinterpret_cast<const void *>(&k_rotate), 256, 0);
+    const long long grid = launch_grid(L, reinterpret_cast<const void *>(&k_rotate), kRotThreads, 0);
     if (grid <= 0 || grid > 0x7fffffffLL) return SKEI_ERANGE;
-    hipLaunchKernelGGL(k_rotate, dim3((unsigned)grid), dim3(256), 0, st, L);
+    hipLaunchKernelGGL(k_rotate, dim3((unsigned)grid), dim3(kRotThreads), 0, st, L);
     return check_launch();
 }
 
