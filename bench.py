@@ -194,11 +194,12 @@ def main():
     value = rays_per_step / (ms_per_step * 1e-3) / 1e9
     flops = algorithmic_flops(dominant, w, widths)
     achieved = flops / (dom_ms * 1e-3) / 1e12
+    traffic, l2_hit = traffic_for(dominant, tuned[dominant][1])
     roofline = {
         "bound": "alu", "kernel": dominant, "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
         "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
         "frac_nonpacked": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4),
-        "launch_ms": round(dom_ms, 5), "traffic": traffic_for(dominant),
+        "launch_ms": round(dom_ms, 5), "traffic": traffic, "l2_hit_rate": l2_hit,
         "gather_equiv_hbm_frac": round(gather_equiv_bytes(dominant, w, widths) / (dom_ms * 1e-3) / 1e9
                                        / PEAK_HBM_GBS, 4),
     }
@@ -297,20 +298,21 @@ def serving_leg(args):
     return res
 
 
-def traffic_for(kernel):
-    """HBM bytes per launch from committed rocprofv3 --pmc summaries, if they
-    were taken on the current kernel source; else None."""
+def traffic_for(stage, shape):
+    """HBM bytes per launch and L2 hit rate of a stage's kernel, from the
+    committed rocprofv3 --pmc summary, if it was taken on the current kernel
+    source and the same tuned launch shape; else (None, None)."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(path):
-        return None
+        return None, None
     try:
         rec = json.load(open(path))
-        ent = rec.get(kernel)
-        if not ent or ent.get("source_sha") != source_sha():
-            return None
-        return ent.get("bytes_per_launch")
+        ent = rec.get(stage)
+        if not ent or rec.get("source_sha") != source_sha() or ent.get("shape") != shape:
+            return None, None
+        return ent.get("bytes_per_launch"), ent.get("l2_hit")
     except Exception:
-        return None
+        return None, None
 
 
 def source_sha():
