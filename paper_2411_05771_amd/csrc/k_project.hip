@@ -243,13 +243,15 @@ __device__ __forceinline__ void zero_tail(float *buf, int pitch, int R, int Rc)
 // KIND kFwd: y[b][r][k] = (1/w) sum_M lerp(line_M, u(k, M))       (Joseph A_S)
 //   resid jobs: y = yfull[b][idx[r]][k] - that, in double; partial[item] = sum y^2.
 // KIND kBpT: q[b][r][k] = sum_M sum_j Lambda(w (j - u(k, M))) line_M[j]    (B_S^T)
-//   The pixels within unit distance of the ray in s are the (at most three)
-//   entries within 1/w of u; the four candidates j0-1 .. j0+2 cover them.
+//   The pixels within unit distance of the ray in s are the entries within
+//   1/w <= sqrt(2) of u.  With j1 = round(u) and g = u - j1 in [-1/2, 1/2),
+//   j1 -+ 2 lie at least 3/2 away, so the three taps j1-1, j1, j1+1 cover
+//   them: weights 1 - w (1 + g), 1 - w |g|, 1 - w (1 - g), clamped at 0.
 // ---------------------------------------------------------------------------
 template <int KIND, int RPT, int U, typename OUT>
 __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float *lds)
 {
-    // Lowest tap entry read: j0 for the forward walk, j0 - 1 for B^T; taps
+    // Lowest tap entry read: j0 for the forward walk, j1 - 1 for B^T; taps
     // below -kLinePad (and above n + 1) are clamped onto the zero borders.
     constexpr int kBias = KIND == kFwd ? kLinePad : kLinePad - 1;
     __shared__ AngleRow ang[kMaxG];
@@ -312,7 +314,7 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
         // Rays of the other branch (and padding rays) are parked far outside
         // the image with a zero step: they read zero borders and add nothing.
         int64_t u[RPT], du[RPT];
-        float s0[RPT], s1[RPT], wg[RPT], c1[RPT], c2[RPT];
+        float s0[RPT], s1[RPT], wg[RPT], cm[RPT], cp[RPT], hw[RPT];
         int lo = n, hi = -1;
 #pragma unroll
         for (int q = 0; q < RPT; q++) {
@@ -327,13 +329,19 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
             }
             // biased by kBias entries so that tap indices are non-negative
             // inside the padded line; one unsigned min clamps both ends
-            u[q] = act ? A.base_fx + (int64_t)rk[q] * A.inv_fx + ((int64_t)kBias << 32) : -((int64_t)1 << 44);
+            // (B^T rounds to the nearest entry: its position carries +1/2)
+            constexpr int64_t kHalf = KIND == kFwd ? 0 : (int64_t)1 << 31;
+            u[q] = act ? A.base_fx + (int64_t)rk[q] * A.inv_fx + ((int64_t)kBias << 32) + kHalf
+                       : -((int64_t)1 << 44);
             du[q] = act ? A.du_fx : 0;
             s0[q] = 0.0f;
             s1[q] = 0.0f;
+            // with F = frac(u + 1/2) = g + 1/2:  1 - w (1 + g) = cm - w F,
+            // 1 - w (1 - g) = cp + w F, and w g = w F + hw
             wg[q] = A.w * kTwoM32;
-            c1[q] = 1.0f - A.w;
-            c2[q] = 1.0f - 2.0f * A.w;
+            cm[q] = 1.0f - 0.5f * A.w;
+            cp[q] = 1.0f - 1.5f * A.w;
+            hw[q] = -0.5f * A.w;
         }
         lo = __builtin_amdgcn_readfirstlane(wave_min(lo));
         hi = __builtin_amdgcn_readfirstlane(wave_max(hi));
@@ -401,15 +409,13 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
                                 s1[q] = fmaf(fi, t1 - t0, s1[q]);
                             } else {
                                 const float *e = line + jb - 1;
-                                const float gq = fi * wg[q];
-                                const float wa = fmaxf(c1[q] - gq, 0.0f);   // j0-1: 1 - w (1 + f)
-                                const float wb = 1.0f - gq;                 // j0  : 1 - w f
-                                const float wc = c1[q] + gq;                // j0+1: 1 - w (1 - f)
-                                const float wd = fmaxf(c2[q] + gq, 0.0f);   // j0+2: 1 - w (2 - f)
-                                float ls = wa * e[0];
-                                ls = fmaf(wb, e[1], ls);
-                                ls = fmaf(wc, e[2], ls);
-                                ls = fmaf(wd, e[3], ls);
+                                // the clamps fold into the FMAs (weights are <= 1)
+                                const float wm = __builtin_amdgcn_fmed3f(fmaf(-fi, wg[q], cm[q]), 0.0f, 1.0f);
+                                const float w0 = 1.0f - fabsf(fmaf(fi, wg[q], hw[q]));
+                                const float wp = __builtin_amdgcn_fmed3f(fmaf(fi, wg[q], cp[q]), 0.0f, 1.0f);
+                                float ls = wm * e[0];
+                                ls = fmaf(w0, e[1], ls);
+                                ls = fmaf(wp, e[2], ls);
                                 accd[q] += (double)ls;
                             }
                         }
