@@ -81,7 +81,7 @@ EiSizes ei_sizes(const skei_geom *g, int batch, int m_mc, int m, int copies)
     s.img = bc * nn;
     s.sino = bc * (size_t)m * g->n_det;
     s.mc = (size_t)batch * m_mc * g->n_det;
-    s.part_mc = ray_items_max(g, batch, m_mc, g->tune_fwd);
+    s.part_mc = (size_t)batch * m_mc;   // one per r_MC row
     s.part_ei = gather_items(g->n, (int)bc);
     return s;
 }
@@ -144,25 +144,22 @@ int ei_problem_jobs(const skei_ei_problem &p, const EiBuffers &b, const RayChoic
         tb = RayTune{};
         tb.lines = bpt.lines;
     }
-    if ((rc = make_ray_job(g, b.z, b.zT, bc, p.angle_idx, m, b.ys, nullptr, nullptr, tf, fwd.rpt, J.fwd[0],
+    if ((rc = make_ray_job(g, b.z, b.zT, bc, p.angle_idx, m, b.ys, nullptr, tf, fwd.rpt, J.fwd[0],
                            J.fwd_shape[0])))
         return rc;
-    // The MC residual's sums of squares are per work item, so its items take
-    // one fixed shape (one angle, segments of at most 512 detectors) whatever
-    // the tuning: the loss is then bitwise the same under every launch shape.
-    RayTune mc_shape;
-    mc_shape.group = 1;
-    mc_shape.split = (g->n_det + 511) / 512;
-    mc_shape.lines = tf.lines;   // chunk height does not change the arithmetic
-    if ((rc = make_ray_job(g, p.x, b.xT, batch, p.mc_idx, m_mc, b.rmc, p.y, b.pmc, mc_shape, 0, J.fwd[1],
+    if ((rc = make_ray_job(g, p.x, b.xT, batch, p.mc_idx, m_mc, b.rmc, p.y, tf, fwd.rpt, J.fwd[1],
                            J.fwd_shape[1])))
         return rc;
-    if ((size_t)J.fwd[1].items > b.n_pmc) return SKEI_ERANGE;
-    J.ramp = make_ramp_job(g, b.ys, (long long)bc * m, 1.0f, b.qs);
+    // ||r_MC||^2 as row sums in a fixed order (in the ramp launch): the loss
+    // is bitwise the same under every launch shape
+    const long long mc_rows = (long long)batch * m_mc;
+    if ((size_t)mc_rows > b.n_pmc) return SKEI_ERANGE;
+    J.ramp[0] = make_ramp_job(g, b.ys, (long long)bc * m, 1.0f, b.qs);
+    J.ramp[1] = make_row_sumsq_job(g, b.rmc, mc_rows, b.pmc);
     J.bp = make_gather_job(g, b.qs, bc, p.angle_idx, m, pim, b.r, b.z, b.pei, b.rT);
     J.red = RedJob{};
     J.red.p0 = b.pmc;
-    J.red.n0 = J.fwd[1].items;
+    J.red.n0 = mc_rows;
     J.red.w0 = 1.0;
     J.red.p1 = b.pei;
     J.red.n1 = J.bp.items;
@@ -172,7 +169,7 @@ int ei_problem_jobs(const skei_ei_problem &p, const EiBuffers &b, const RayChoic
     // backward: ysd = B_S^T r ; qs = (pi/m) H ysd ; z = r - A_S^T qs ;
     //           amc = A_mc^T r_MC ; grad = (2 lambda / C) sum_c T_c^T z - 2 amc
     J.grad = p.grad != nullptr;
-    if ((rc = make_ray_job(g, b.r, b.rT, bc, p.angle_idx, m, b.ysd, nullptr, nullptr, tb, bpt.rpt, J.bpt,
+    if ((rc = make_ray_job(g, b.r, b.rT, bc, p.angle_idx, m, b.ysd, nullptr, tb, bpt.rpt, J.bpt,
                            J.bpt_shape)))
         return rc;
     J.rampT = make_ramp_job(g, b.ysd, (long long)bc * m, pim, b.qs);
@@ -204,7 +201,7 @@ int skei_radon_fwd(const skei_geom *g, const float *x, int batch, const int32_t 
 {
     int rc = check_geom_op(g, x, batch, angle_idx, m, y);
     if (rc) return rc;
-    return launch_radon_fwd(g, x, nullptr, batch, angle_idx, m, y, nullptr, nullptr, g->tune_fwd, S(stream));
+    return launch_radon_fwd(g, x, nullptr, batch, angle_idx, m, y, nullptr, g->tune_fwd, S(stream));
 }
 
 int skei_radon_adj(const skei_geom *g, const float *y, int batch, const int32_t *angle_idx, int m, float *x,
@@ -332,7 +329,7 @@ int skei_ei_loss_grad(const skei_geom *g, const float *x, const float *y, int ba
     if ((rc = staged(SKEI_STAGE_FWD, st, [&] { return ray_run(kRayFwd, false, fwd_sh, inline_jobs(J.fwd, 2), st); })))
         return rc;
     if ((rc = staged(SKEI_STAGE_RAMP, st,
-                     [&] { return ramp_run(false, ramp_block(g->n_det), ramp_shm(g->n_det), inline_jobs(&J.ramp, 1), st); })))
+                     [&] { return ramp_run(false, ramp_block(g->n_det), ramp_shm(g->n_det), inline_jobs(J.ramp, 2), st); })))
         return rc;
     if ((rc = staged(SKEI_STAGE_BP_RESID, st,
                      [&] { return gather_run(kGatherBackproject, gather_groups_auto(m), inline_jobs(&J.bp, 1), st); })))

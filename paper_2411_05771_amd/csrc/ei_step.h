@@ -25,13 +25,13 @@ size_t ei_workspace_bytes(const skei_geom *g, int batch, int m_mc, int m, int co
 // false when `bytes` is too small.
 bool ei_carve(const skei_geom *g, int batch, int m_mc, int m, int copies, void *work, size_t bytes, EiBuffers &b);
 
-// All jobs of one problem's step.  Two-job stages (ROTATE, FWD, ADJ) hold the
-// sketch/copies job first and the MC / plain-image job second.
+// All jobs of one problem's step.  Two-job stages (ROTATE, FWD, RAMP, ADJ)
+// hold the sketch/copies job first and the MC / plain-image job second.
 struct EiJobs {
     RotJob rot[2];
     RayJob fwd[2];
     RayShape fwd_shape[2];
-    RampJob ramp;
+    RampJob ramp[2];   // H ys, and the row sums of squares of r_MC
     GatherJob bp;
     RedJob red;
     RayJob bpt;

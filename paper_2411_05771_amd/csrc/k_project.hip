@@ -53,7 +53,7 @@ int line_pitch(int n) { return ((n + 2 * kLinePad) + 3) & ~3; }
 }  // namespace
 
 int make_ray_job(const skei_geom *g, const float *x, const float *xT, int batch, const int32_t *idx, int m, void *y,
-                 const float *yfull, double *partial, const RayTune &t, int rpt_cap, RayJob &J, RayShape &shape)
+                 const float *yfull, const RayTune &t, int rpt_cap, RayJob &J, RayShape &shape)
 {
     const int n = g->n, nd = g->n_det;
     const long long base_items = (long long)batch * m;
@@ -83,7 +83,6 @@ int make_ray_job(const skei_geom *g, const float *x, const float *xT, int batch,
     J.tab = g->tab;
     J.y = y;
     J.yfull = yfull;
-    J.partial = partial;
     J.n = n;
     J.n_det = nd;
     J.m = m;
@@ -118,13 +117,6 @@ int make_ray_job(const skei_geom *g, const float *x, const float *xT, int batch,
     return SKEI_OK;
 }
 
-size_t ray_items_max(const skei_geom *g, int batch, int m, const RayTune &t)
-{
-    // G >= 1 and at most max(2, ceil(N_det / 256), split) segments per angle
-    const int nseg = std::max(std::max(2, (g->n_det + kBlock - 1) / kBlock), t.split);
-    return (size_t)batch * m * nseg;
-}
-
 namespace {
 
 __device__ __forceinline__ int wave_min(int v)
@@ -135,11 +127,6 @@ __device__ __forceinline__ int wave_min(int v)
 __device__ __forceinline__ int wave_max(int v)
 {
     for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-    return v;
-}
-__device__ __forceinline__ double wave_sum(double v)
-{
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
 }
 
@@ -159,32 +146,49 @@ __device__ __forceinline__ void ray_range(float u0, float du, int n, int &lo, in
     hi = (int)fminf(ceilf(fmaxf(t1, t2)) + 1.0f, (float)(n - 1));
 }
 
-// Minor-axis span [cl, cl+W) within [0, n) touched by the group's rays of one
-// pass over lines [M0, M0+Rc); widened by 3 entries each side, and aligned
-// to 4 entries for 16-byte DMA lanes.
-__device__ __forceinline__ void chunk_span(const AngleRow *ang, int gcount, int pass, int k0, int k1, int M0, int Rc,
-                                           int n, int &cl, int &W)
+// Minor-axis extent of the group's rays of one pass, per listed angle: lane
+// g (< gcount) holds angle g's extent at line 0 over detectors [k0, k1] and
+// its drift per line; lanes without an angle of this pass hold an empty one.
+struct Span {
+    float amin, amax, du;
+};
+
+__device__ __forceinline__ Span span_setup(const AngleRow *ang, int gcount, int pass, int k0, int k1)
 {
-    float umin = 3.0e38f, umax = -3.0e38f;
-    const float fk0 = (float)k0, fk1 = (float)k1, fm0 = (float)M0, fm1 = (float)(M0 + Rc - 1);
-    for (int g = 0; g < gcount; g++) {
+    const int g = threadIdx.x & 63;
+    Span sp{3.0e38f, -3.0e38f, 0.0f};
+    if (g < gcount && ang[g].rows == pass) {
         const AngleRow &A = ang[g];
-        if (A.rows != pass) continue;
-        const float a0 = fmaf(fk0, A.inv_m, A.base), a1 = fmaf(fk1, A.inv_m, A.base);
-        const float c00 = fmaf(fm0, A.du, a0), c01 = fmaf(fm1, A.du, a0);
-        const float c10 = fmaf(fm0, A.du, a1), c11 = fmaf(fm1, A.du, a1);
-        umin = fminf(umin, fminf(fminf(c00, c01), fminf(c10, c11)));
-        umax = fmaxf(umax, fmaxf(fmaxf(c00, c01), fmaxf(c10, c11)));
+        const float a0 = fmaf((float)k0, A.inv_m, A.base), a1 = fmaf((float)k1, A.inv_m, A.base);
+        sp.amin = fminf(a0, a1);
+        sp.amax = fmaxf(a0, a1);
+        sp.du = A.du;
     }
-    const float lo = fmaxf(floorf(umin) - 3.0f, 0.0f);
-    const float hi = fminf(floorf(umax) + 4.0f, (float)(n - 1));
-    if (!(hi >= lo)) {
+    return sp;
+}
+
+// Minor-axis span [cl, cl+W) within [0, n) touched by the group's rays of one
+// pass over lines [M0, M0+Rc): the union of the angles' extents (gathered
+// across lanes with readlane, no LDS traffic), widened by 3 entries each
+// side, and aligned to 4 entries for 16-byte DMA lanes.
+__device__ __forceinline__ void chunk_span(const Span &sp, int gcount, int M0, int Rc, int n, int &cl, int &W)
+{
+    const float d0 = sp.du * (float)M0, d1 = sp.du * (float)(M0 + Rc - 1);
+    const float lo = sp.amin + fminf(d0, d1), hi = sp.amax + fmaxf(d0, d1);
+    float umin = 3.0e38f, umax = -3.0e38f;
+    for (int g = 0; g < gcount; g++) {
+        umin = fminf(umin, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lo), g)));
+        umax = fmaxf(umax, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hi), g)));
+    }
+    const float flo = fmaxf(floorf(umin) - 3.0f, 0.0f);
+    const float fhi = fminf(floorf(umax) + 4.0f, (float)(n - 1));
+    if (!(fhi >= flo)) {
         cl = 0;
         W = 0;
         return;
     }
-    cl = ((int)lo) & ~3;
-    W = (int)hi - cl + 1;
+    cl = ((int)flo) & ~3;
+    W = (int)fhi - cl + 1;
 }
 
 // DMA of lines [M0, M0+Rc), positions [cl, cl+W), into LDS buffer `buf`
@@ -241,7 +245,7 @@ __device__ __forceinline__ void zero_tail(float *buf, int pitch, int R, int Rc)
 
 // ---------------------------------------------------------------------------
 // KIND kFwd: y[b][r][k] = (1/w) sum_M lerp(line_M, u(k, M))       (Joseph A_S)
-//   resid jobs: y = yfull[b][idx[r]][k] - that, in double; partial[item] = sum y^2.
+//   resid jobs: y = yfull[b][idx[r]][k] - that, in double.
 // KIND kBpT: q[b][r][k] = sum_M sum_j Lambda(w (j - u(k, M))) line_M[j]    (B_S^T)
 //   The pixels within unit distance of the ray in s are the entries within
 //   1/w <= sqrt(2) of u.  With j1 = round(u) and g = u - j1 in [-1/2, 1/2),
@@ -256,7 +260,6 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
     constexpr int kBias = KIND == kFwd ? kLinePad : kLinePad - 1;
     __shared__ AngleRow ang[kMaxG];
     __shared__ int wrange[2][kWaves];
-    __shared__ double red[kWaves];
 
     const float *__restrict__ x = J.x;
     const float *__restrict__ xT = J.xT;
@@ -264,7 +267,6 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
     const AngleRow *__restrict__ tab = J.tab;
     OUT *__restrict__ y = static_cast<OUT *>(J.y);
     const float *__restrict__ yfull = J.yfull;
-    double *__restrict__ partial = J.partial;
     const int n = J.n, n_det = J.n_det, m = J.m, n_angles = J.n_angles;
     const int G = J.G, nseg = J.nseg, seg = J.seg, ngroups = J.ngroups, R = J.R, pitch = J.pitch;
     const bool resid = KIND == kFwd && J.resid;
@@ -310,6 +312,7 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
         bool any = false;
         for (int g = 0; g < gcount; g++) any |= ang[g].rows == pass;
         if (!any) continue;
+        const Span span = span_setup(ang, gcount, pass, k_begin, k_begin + k_len - 1);
 
         // Rays of the other branch (and padding rays) are parked far outside
         // the image with a zero step: they read zero borders and add nothing.
@@ -365,14 +368,13 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
         // column passes read rows of the transposed image when it is given
         const bool dma_rows = rows || xT != nullptr;
         const float *src = rows || !xT ? img : xT + (size_t)b * n * n;
-        const int k_last = k_begin + k_len - 1;
         const unsigned cap = (unsigned)(n + 1 + kBias);
         if (blo <= bhi) {
             const int c_first = blo / R, c_last = bhi / R;
             {
                 const int M0 = c_first * R, Rc = min(R, n - M0);
                 int cl, W;
-                chunk_span(ang, gcount, pass, k_begin, k_last, M0, Rc, n, cl, W);
+                chunk_span(span, gcount, M0, Rc, n, cl, W);
                 zero_tail(lds, pitch, R, Rc);
                 stage_dma(lds, pitch, src, n, dma_rows, M0, Rc, cl, W);
                 dma_wait();
@@ -384,7 +386,7 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
                 if (c < c_last) {                 // next chunk streams in while this one is marched
                     const int M1 = M0 + R, Rc1 = min(R, n - M1);
                     int cl, W;
-                    chunk_span(ang, gcount, pass, k_begin, k_last, M1, Rc1, n, cl, W);
+                    chunk_span(span, gcount, M1, Rc1, n, cl, W);
                     float *nb = lds + (cur ^ 1) * buf_stride;
                     zero_tail(nb, pitch, R, Rc1);
                     stage_dma(nb, pitch, src, n, dma_rows, M1, Rc1, cl, W);
@@ -446,7 +448,6 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
         }
     }
 
-    double ss = 0.0;
 #pragma unroll
     for (int q = 0; q < RPT; q++) {
         if (rg[q] < 0) continue;
@@ -456,25 +457,12 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
             double v = accd[q] * A.scale;
             if (resid) {
                 const int a = idx[r0 + rg[q]];
-                v = (double)yfull[((size_t)b * n_angles + a) * n_det + rk[q]] - v;
-                const float vf = (float)v;
-                ss += (double)vf * (double)vf;
-                y[o] = vf;
+                y[o] = (float)((double)yfull[((size_t)b * n_angles + a) * n_det + rk[q]] - v);
             } else {
                 y[o] = (OUT)v;
             }
         } else {
             y[o] = (OUT)accd[q];
-        }
-    }
-    if (resid) {
-        ss = wave_sum(ss);
-        if ((tid & 63) == 0) red[tid >> 6] = ss;
-        __syncthreads();
-        if (tid == 0) {
-            double s = 0.0;
-            for (int w = 0; w < kWaves; w++) s += red[w];
-            partial[item] = s;
         }
     }
 }
@@ -530,11 +518,11 @@ int ray_run(int kind, bool out_double, const RayShape &sh, const JobList<RayJob>
 }
 
 int launch_radon_fwd(const skei_geom *g, const float *x, const float *xT, int batch, const int32_t *idx, int m,
-                     float *y, const float *yfull, double *partial, const RayTune &tune, hipStream_t st)
+                     float *y, const float *yfull, const RayTune &tune, hipStream_t st)
 {
     RayJob J;
     RayShape sh;
-    int rc = make_ray_job(g, x, xT, batch, idx, m, y, yfull, partial, tune, 0, J, sh);
+    int rc = make_ray_job(g, x, xT, batch, idx, m, y, yfull, tune, 0, J, sh);
     if (rc) return rc;
     return ray_run(kRayFwd, false, sh, inline_jobs(&J, 1), st);
 }
@@ -544,7 +532,7 @@ int launch_bp_T(const skei_geom *g, const float *x, const float *xT, int batch, 
 {
     RayJob J;
     RayShape sh;
-    int rc = make_ray_job(g, x, xT, batch, idx, m, qd ? (void *)qd : (void *)qf, nullptr, nullptr, tune, 0, J, sh);
+    int rc = make_ray_job(g, x, xT, batch, idx, m, qd ? (void *)qd : (void *)qf, nullptr, tune, 0, J, sh);
     if (rc) return rc;
     return ray_run(kRayBpT, qd != nullptr, sh, inline_jobs(&J, 1), st);
 }

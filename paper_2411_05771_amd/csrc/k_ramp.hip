@@ -42,6 +42,21 @@ __device__ __forceinline__ void ramp_item(const RampJob &J, long long r, double 
     const int E = ramp_taps(n_det), ES = E / S;
     const int pad = ramp_pad(n_det);
     const int tid = threadIdx.x, bs = blockDim.x;
+    if (J.partial) {
+        // row sum of squares: wave 0 alone, lane-strided then a butterfly, so
+        // the order does not depend on the launch's block size
+        if (tid < 64) {
+            const IN *p = static_cast<const IN *>(J.p) + (size_t)r * n_det;
+            double s = 0.0;
+            for (int k = tid; k < n_det; k += 64) {
+                const double v = (double)p[k];
+                s = fma(v, v, s);
+            }
+            for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+            if (tid == 0) J.partial[r] = s;
+        }
+        return;
+    }
     const int per = ramp_group(n_det);          // threads per tap group (whole waves)
     const int len = n_det + 2 * pad;
     double *part = row + len + (len >> 3) + 1;  // [S - 1][per * V] partial sums
@@ -147,6 +162,16 @@ RampJob make_ramp_job(const skei_geom *g, const void *p, long long rows, float s
     J.hodd = g->hodd;
     J.n_det = g->n_det;
     J.scale = scale;
+    J.items = rows;
+    return J;
+}
+
+RampJob make_row_sumsq_job(const skei_geom *g, const float *p, long long rows, double *partial)
+{
+    RampJob J{};
+    J.p = p;
+    J.partial = partial;
+    J.n_det = g->n_det;
     J.items = rows;
     return J;
 }

@@ -143,7 +143,8 @@ int plan_build(skei_ei_plan *P)
         for (int k = 0; k < 2; k++) {
             t[SKEI_STAGE_FWD].ray = merge_shapes(t[SKEI_STAGE_FWD].ray, J.fwd_shape[k]);
         }
-        ramp.push_back(J.ramp);
+        ramp.push_back(J.ramp[0]);
+        ramp.push_back(J.ramp[1]);
         bp.push_back(J.bp);
         max_m_bp = std::max(max_m_bp, p.m);
         red.push_back(J.red);

@@ -57,7 +57,6 @@ int check_launch();   // maps hipGetLastError to SKEI_OK / SKEI_ELAUNCH
 // Joseph forward projection (KIND fwd) or B_S^T (KIND bpT) over listed angles.
 //   fwd, resid = 0: y[b][r][k] = (A_S x[b])[r][k]
 //   fwd, resid = 1: y[b][r][k] = yfull[b][idx[r]][k] - (A_S x[b])[r][k]   (in double);
-//                   partial[item] = sum of y^2 over the item's rays
 //   bpT:            y[b][r][k] = (B_S^T x[b])[r][k]  (unscaled)
 // xT (optional): the images transposed (xT[b][j][i] = x[b][i][j]); when given,
 // column-stepping angles stage rows of xT instead of gathering columns of x.
@@ -69,7 +68,6 @@ struct RayJob {
     const AngleRow *tab;
     void *y;                 // float or double, by launch
     const float *yfull;
-    double *partial;
     int n, n_det, m, n_angles;
     int G, nseg, seg, ngroups;
     int R, pitch, resid, pad_;
@@ -94,9 +92,12 @@ struct GatherJob {
 };
 
 // Ram-Lak filter along detector rows: q = scale * H p.  An item is one row.
+// With `partial` set the job instead sums the squares of each row of p:
+// partial[row] = sum_k p[row][k]^2, in double, in a fixed order.
 struct RampJob {
     const void *p;           // float or double, by launch
     float *q;
+    double *partial;
     const double *hodd;
     int n_det;
     float scale;
@@ -177,7 +178,7 @@ struct JobList {
 // used to cut work lists into XCD ranges of about equal cost.
 inline double item_cost(const RayJob &j) { return (double)j.G * j.seg * j.n + 4.0 * j.n * j.n / (j.R > 0 ? j.R : 1); }
 inline double item_cost(const GatherJob &j) { return 256.0 * (j.m + 8); }
-inline double item_cost(const RampJob &j) { return (double)j.n_det * (j.n_det / 2 + 4); }
+inline double item_cost(const RampJob &j) { return j.partial ? (double)j.n_det : (double)j.n_det * (j.n_det / 2 + 4); }
 inline double item_cost(const RotJob &j) { return j.cs ? 256.0 * 4 : 256.0; }
 inline double item_cost(const RotAdjJob &j) { return 64.0 * 9 * j.copies; }
 inline double item_cost(const RedJob &j) { return (double)(j.n0 + j.n1); }
@@ -281,10 +282,8 @@ struct RayTune {
 // rpt_cap > 0 sizes G and the segments to fill at most rpt_cap * 256 rays per
 // workgroup (tune.group / tune.split still win).
 int make_ray_job(const struct ::skei_geom *g, const float *x, const float *xT, int batch, const int32_t *idx,
-                 int m, void *y, const float *yfull, double *partial, const RayTune &tune, int rpt_cap,
+                 int m, void *y, const float *yfull, const RayTune &tune, int rpt_cap,
                  RayJob &job, RayShape &shape);
-// Upper bound of a ray job's items for any tuning (partial-sum buffers).
-size_t ray_items_max(const struct ::skei_geom *g, int batch, int m, const RayTune &tune);
 
 GatherJob make_gather_job(const struct ::skei_geom *g, const float *in, int batch, const int32_t *idx, int m,
                           float scale, float *out, const float *other, double *partial, float *outT);
@@ -292,6 +291,8 @@ size_t gather_items(int n, int batch);
 int gather_groups_auto(int m);   // default GA for m listed angles
 
 RampJob make_ramp_job(const struct ::skei_geom *g, const void *p, long long rows, float scale, float *q);
+// Row sums of squares of p [rows][N_det] (float) into partial[rows]; runs in a ramp launch.
+RampJob make_row_sumsq_job(const struct ::skei_geom *g, const float *p, long long rows, double *partial);
 int ramp_block(int n_det);      // threads per row
 size_t ramp_shm(int n_det);     // LDS bytes per row
 
@@ -301,7 +302,7 @@ RotAdjJob make_rot_adj_job(const float *h, int batch, int copies, int n, const f
 
 // Convenience wrappers: one job, inline mode.
 int launch_radon_fwd(const skei_geom *g, const float *x, const float *xT, int batch, const int32_t *idx, int m,
-                     float *y, const float *yfull, double *partial, const RayTune &tune, hipStream_t st);
+                     float *y, const float *yfull, const RayTune &tune, hipStream_t st);
 int launch_bp_T(const skei_geom *g, const float *x, const float *xT, int batch, const int32_t *idx, int m,
                 float *qf, double *qd, const RayTune &tune, hipStream_t st);
 int launch_gather(int kind, const skei_geom *g, const float *in, int batch, const int32_t *idx, int m, float scale,
