@@ -32,8 +32,9 @@ struct GatherAngle {
 };
 
 // A workgroup holds a 16 x 16 tile x GA angle groups; each thread owns PPT
-// pixels of the tile (pixels px, px + 256/PPT, ...), so the per-angle
-// constants and window staging are shared by PPT pixels.  The listed angles
+// pixels of one tile row (columns dx, dx + 16/PPT, ...), so the per-angle
+// constants, window staging and the row's share of the position are shared
+// by PPT pixels.  The listed angles
 // are split into four fixed classes (r % 4); each class is summed in
 // increasing r, and the four class sums are added in a fixed order.  Thread
 // (pixel group, ga) owns the classes ga, ga + GA, ...  Positions are relative
@@ -46,6 +47,7 @@ template <int KIND, int GA, int PPT>
 __device__ __forceinline__ void gather_item(const GatherJob &J, long long item)
 {
     constexpr int TILE = 16, NPIX = TILE * TILE, TPG = NPIX / PPT, BS = TPG * GA, WIN = 2 * TILE;
+    constexpr int CW = TILE / PPT;   // column step between a thread's pixels
     constexpr int NC = kClasses / GA;
     __shared__ GatherAngle prm[kAngleChunk];
     __shared__ int kst[kAngleChunk];                  // first detector of each window
@@ -65,13 +67,12 @@ __device__ __forceinline__ void gather_item(const GatherJob &J, long long item)
     const int i0 = (tile / tiles_x) * TILE, j0 = (tile % tiles_x) * TILE;
     const int tid = threadIdx.x;
     const int pg = tid % TPG, ga = tid / TPG;
-    double fdx[PPT], fdy[PPT];
+    // pixel v of this thread: row pg / CW, column pg % CW + v CW
+    auto pix = [&](int v) { return (pg / CW) * TILE + pg % CW + v * CW; };
+    const double fdy = (double)(pg / CW);
+    double fdx[PPT];
 #pragma unroll
-    for (int v = 0; v < PPT; v++) {
-        const int px = pg + v * TPG;
-        fdx[v] = (double)(px % TILE);
-        fdy[v] = (double)(px / TILE);
-    }
+    for (int v = 0; v < PPT; v++) fdx[v] = (double)(pg % CW + v * CW);
     const double cN = 0.5 * (n - 1), cD = 0.5 * (n_det - 1);
     const float *src = J.in + (size_t)b * m * n_det;
 
@@ -114,17 +115,19 @@ __device__ __forceinline__ void gather_item(const GatherJob &J, long long item)
                 if (a < Ac) {
                     const GatherAngle p = prm[a];
                     const float2 *wa_row = win + a * WIN;
+                    const double trow = fma(fdy, p.s, p.t0);
 #pragma unroll
                     for (int v = 0; v < PPT; v++) {
                         // window-local detector coordinate in double: exact to ~1e-15 px
-                        const double tl = fma(fdx[v], p.c, fma(fdy[v], p.s, p.t0));
+                        const double tl = fma(fdx[v], p.c, trow);
                         const int k0 = (int)tl;                          // 1 <= tl < WIN - 1 by construction
                         const float f = (float)__builtin_amdgcn_fract(tl);
                         const float2 e = wa_row[k0];
                         if (KIND == kJosephAdj) {
-                            // weights Lambda((k - t)/w)/w for k = k0, k0+1 (the 1/w^2 is in the window)
-                            const float wa = fmaxf(p.w - f, 0.0f);
-                            const float wb = fmaxf(f + p.wm1, 0.0f);
+                            // weights Lambda((k - t)/w)/w for k = k0, k0+1 (the 1/w^2 is in the
+                            // window); both are <= 1, so the clamps fold into the add
+                            const float wa = __builtin_amdgcn_fmed3f(p.w - f, 0.0f, 1.0f);
+                            const float wb = __builtin_amdgcn_fmed3f(f + p.wm1, 0.0f, 1.0f);
                             acc[c][v] = fmaf(wa, e.x, acc[c][v]);
                             acc[c][v] = fmaf(wb, e.y, acc[c][v]);
                         } else {
@@ -144,11 +147,11 @@ __device__ __forceinline__ void gather_item(const GatherJob &J, long long item)
 #pragma unroll
         for (int c = 0; c < NC; c++)
 #pragma unroll
-            for (int v = 0; v < PPT; v++) part[ga + c * GA][pg + v * TPG] = acc[c][v];
+            for (int v = 0; v < PPT; v++) part[ga + c * GA][pix(v)] = acc[c][v];
         __syncthreads();
 #pragma unroll
         for (int v = 0; v < PPT; v++) {
-            const int px = pg + v * TPG;
+            const int px = pix(v);
             sum[v] = ((part[0][px] + part[1][px]) + part[2][px]) + part[3][px];
         }
     }
@@ -157,7 +160,7 @@ __device__ __forceinline__ void gather_item(const GatherJob &J, long long item)
     const bool resid = J.other != nullptr;
 #pragma unroll
     for (int v = 0; v < PPT; v++) {
-        const int px = pg + v * TPG, dx = px % TILE, dy = px / TILE;
+        const int px = pix(v), dx = px % TILE, dy = px / TILE;
         const int i = i0 + dy, j = j0 + dx;
         float out = 0.0f;
         double ss = 0.0;
@@ -180,7 +183,7 @@ __device__ __forceinline__ void gather_item(const GatherJob &J, long long item)
         if (ga == 0) {
 #pragma unroll
             for (int v = 0; v < PPT; v++) {
-                const int px = pg + v * TPG, dx = px % TILE, dy = px / TILE;
+                const int px = pix(v), dx = px % TILE, dy = px / TILE;
                 const int it = j0 + dy, jt = i0 + dx;
                 if (it < n && jt < n) J.outT[((size_t)b * n + it) * n + jt] = tileT[dx][dy];
             }
