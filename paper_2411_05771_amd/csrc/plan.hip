@@ -29,7 +29,7 @@ namespace {
 constexpr int kStages = SKEI_STAGE_COUNT;
 
 struct StageCfg {
-    int dispatch = SKEI_DISPATCH_PERSISTENT;
+    int dispatch = SKEI_DISPATCH_STATIC;
     int shape = 0;
 };
 
@@ -112,8 +112,8 @@ int plan_build(skei_ei_plan *P)
     for (const skei_ei_problem &p : P->probs) max_nd = std::max(max_nd, p.geom->n_det);
     const int def_rpt = max_nd > 400 ? 3 : 2;
     // ray-stage shape code: rays per thread + 100 x chunk height
-    // (B_S^T, with four taps per line, runs best with the higher occupancy of
-    // 8-line chunks by default)
+    // (B_S^T, with three taps per line, runs best with the higher occupancy
+    // of 8-line chunks by default)
     auto choice = [&](int shape, int def_lines) {
         RayChoice c;
         c.own = false;
@@ -349,9 +349,9 @@ int skei_ei_plan_create(const skei_ei_problem *problems, int count, void *work, 
     if (need > 0 && (!work || work_bytes < need)) return work ? SKEI_ESPACE : SKEI_EINVAL;
     skei_ei_plan *P = new (std::nothrow) skei_ei_plan;
     if (!P) return SKEI_ENOMEM;
-    // defaults: long ray-driven items run persistent, short items static
-    for (int s = 0; s < kStages; s++)
-        P->cfg[s].dispatch = is_ray_stage(s) ? SKEI_DISPATCH_PERSISTENT : SKEI_DISPATCH_STATIC;
+    // default: static dispatch (measured ahead of persistent on every stage of
+    // the EI and uneven workloads; the autotuner still tries both)
+    for (int s = 0; s < kStages; s++) P->cfg[s].dispatch = SKEI_DISPATCH_STATIC;
     if (hipGetDevice(&P->device) != hipSuccess) {
         delete P;
         return SKEI_ELAUNCH;
