@@ -20,6 +20,7 @@ namespace {
 
 constexpr int kRampV = 8;   // outputs per thread
 constexpr int kRampS = 4;   // tap groups per output (summed in a fixed order)
+constexpr int kRampSumRows = 4;   // rows per row-sum-of-squares item (one wave each)
 
 // Taps stepped per output: every odd offset below N_det, rounded up to whole
 // groups of 4 taps per tap group.  row = [pad | n_det values | pad] in double
@@ -43,17 +44,19 @@ __device__ __forceinline__ void ramp_item(const RampJob &J, long long r, double 
     const int pad = ramp_pad(n_det);
     const int tid = threadIdx.x, bs = blockDim.x;
     if (J.partial) {
-        // row sum of squares: wave 0 alone, lane-strided then a butterfly, so
-        // the order does not depend on the launch's block size
-        if (tid < 64) {
-            const IN *p = static_cast<const IN *>(J.p) + (size_t)r * n_det;
+        // row sums of squares, kRampSumRows rows per item: wave w takes row
+        // kRampSumRows r + w, lane-strided then a butterfly, so the order does
+        // not depend on the launch's block size (always >= 4 waves)
+        const long long row_i = r * kRampSumRows + (tid >> 6);
+        if (tid < 64 * kRampSumRows && row_i < J.rows) {
+            const IN *p = static_cast<const IN *>(J.p) + (size_t)row_i * n_det;
             double s = 0.0;
-            for (int k = tid; k < n_det; k += 64) {
+            for (int k = tid & 63; k < n_det; k += 64) {
                 const double v = (double)p[k];
                 s = fma(v, v, s);
             }
             for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-            if (tid == 0) J.partial[r] = s;
+            if ((tid & 63) == 0) J.partial[row_i] = s;
         }
         return;
     }
@@ -172,7 +175,8 @@ RampJob make_row_sumsq_job(const skei_geom *g, const float *p, long long rows, d
     J.p = p;
     J.partial = partial;
     J.n_det = g->n_det;
-    J.items = rows;
+    J.rows = rows;
+    J.items = (rows + kRampSumRows - 1) / kRampSumRows;
     return J;
 }
 

@@ -101,6 +101,7 @@ struct RampJob {
     const double *hodd;
     int n_det;
     float scale;
+    long long rows;          // rows of a sum-of-squares job
     long long items;
 };
 
@@ -178,7 +179,7 @@ struct JobList {
 // used to cut work lists into XCD ranges of about equal cost.
 inline double item_cost(const RayJob &j) { return (double)j.G * j.seg * j.n + 4.0 * j.n * j.n / (j.R > 0 ? j.R : 1); }
 inline double item_cost(const GatherJob &j) { return 256.0 * (j.m + 8); }
-inline double item_cost(const RampJob &j) { return j.partial ? (double)j.n_det : (double)j.n_det * (j.n_det / 2 + 4); }
+inline double item_cost(const RampJob &j) { return j.partial ? 4.0 * j.n_det : (double)j.n_det * (j.n_det / 2 + 4); }
 inline double item_cost(const RotJob &j) { return j.cs ? 256.0 * 4 : 256.0; }
 inline double item_cost(const RotAdjJob &j) { return 64.0 * 9 * j.copies; }
 inline double item_cost(const RedJob &j) { return (double)(j.n0 + j.n1); }
