@@ -225,7 +225,8 @@ int skei_ei_plan_run(skei_ei_plan *plan, void *stream);
  *     items from per-XCD queues, then steal from the other XCDs' queues;
  *   SKEI_DISPATCH_STATIC: one workgroup per work item, XCD-major ranges.
  * `shape`: for the ray-driven stages (FWD, BP_T) rays per thread (1..4)
- * plus 100 x the image lines per LDS chunk (0 = built-in, 4, 8 or 16);
+ * plus 100 x the image lines per LDS chunk (0 = built-in, 4, 8 or 16), plus
+ * 10000 for workgroups of three waves instead of four;
  * for the gathers (BP_RESID, ADJ) angle groups per pixel (1, 2, 4) with one
  * pixel per thread, or 10 x groups + 4 (14, 24, 44) with four pixels per
  * thread; 0 keeps the default; ignored by the other stages.  Synchronises the device when

@@ -140,10 +140,12 @@ int ei_problem_jobs(const skei_ei_problem &p, const EiBuffers &b, const RayChoic
     if (!fwd.own) {
         tf = RayTune{};
         tf.lines = fwd.lines;
+        tf.waves = fwd.waves;
     }
     if (!bpt.own) {
         tb = RayTune{};
         tb.lines = bpt.lines;
+        tb.waves = bpt.waves;
     }
     if ((rc = make_ray_job(g, b.z, b.zT, bc, p.angle_idx, m, b.ys, nullptr, tf, fwd.rpt, J.fwd[0],
                            J.fwd_shape[0])))

@@ -37,10 +37,9 @@ namespace {
 typedef __attribute__((address_space(1))) const void gmem_t;
 typedef __attribute__((address_space(3))) void lmem_t;
 
-constexpr int kBlock = 256;                  // threads per workgroup (4 waves)
-constexpr int kWaves = kBlock / 64;
+constexpr int kMaxWaves = 4;                 // waves per workgroup: 3 or 4
 constexpr int kMaxG = 8;                     // listed angles per workgroup
-constexpr int kRaysMax = 4 * kBlock;         // rays per workgroup (4 per thread)
+constexpr int kMaxRpt = 4;                   // rays per thread
 constexpr size_t kLdsBudget = 40 * 1024;     // both staging buffers (default)
 constexpr size_t kLdsMax = 160 * 1024;       // LDS of one CU (gfx950)
 constexpr float kTwoM32 = 2.3283064365386963e-10f;   // 2^-32
@@ -57,7 +56,9 @@ int make_ray_job(const skei_geom *g, const float *x, const float *xT, int batch,
 {
     const int n = g->n, nd = g->n_det;
     const long long base_items = (long long)batch * m;
-    const int cap = rpt_cap > 0 ? std::min(rpt_cap, kRaysMax / kBlock) * kBlock : kRaysMax;
+    const int waves = t.waves == 3 ? 3 : 4;
+    const int block = 64 * waves;
+    const int cap = (rpt_cap > 0 ? std::min(rpt_cap, kMaxRpt) : kMaxRpt) * block;
     int nseg = t.split > 0 ? t.split
                            : rpt_cap > 0 ? (nd + cap - 1) / cap
                                          : ((base_items < 512 && nd >= 128) ? 2 : 1);
@@ -66,7 +67,7 @@ int make_ray_job(const skei_geom *g, const float *x, const float *xT, int batch,
     if (t.group > 0)
         G = t.group;
     else
-        G = std::max(1, (rpt_cap > 0 ? cap : 2 * kBlock) / ((nd + nseg - 1) / nseg));
+        G = std::max(1, (rpt_cap > 0 ? cap : 2 * block) / ((nd + nseg - 1) / nseg));
     G = std::max(1, std::min(std::min(G, kMaxG), m));
     for (;;) {
         const int seg = (nd + nseg - 1) / nseg;
@@ -111,9 +112,10 @@ int make_ray_job(const skei_geom *g, const float *x, const float *xT, int batch,
     shape.unroll = U;
     J.resid = yfull != nullptr;
     J.items = (long long)batch * J.ngroups * J.nseg;
-    shape.rpt = (G * J.seg + kBlock - 1) / kBlock;
+    shape.rpt = (G * J.seg + block - 1) / block;
+    shape.waves = waves;
     shape.shm = 2 * (size_t)R * J.pitch * sizeof(float);
-    if (shape.shm > kLdsMax || shape.rpt > kRaysMax / kBlock) return SKEI_ERANGE;
+    if (shape.shm > kLdsMax || shape.rpt > kMaxRpt) return SKEI_ERANGE;
     return SKEI_OK;
 }
 
@@ -196,22 +198,23 @@ __device__ __forceinline__ void chunk_span(const Span &sp, int gcount, int M0, i
 // 16 bytes (4 consecutive entries; n % 4 == 0 and cl % 4 == 0), 256 entries
 // per wave instruction.  Columns: each lane gathers one entry of the column,
 // 64 consecutive rows per wave instruction.  Lanes past the span are masked.
+template <int NW>
 __device__ __forceinline__ void stage_dma(float *buf, int pitch, const float *__restrict__ img, int n, bool rows,
                                           int M0, int Rc, int cl, int W)
 {
     if (W <= 0) return;
     const int lane = threadIdx.x & 63;
     // wave-uniform bookkeeping lives in scalar registers: wave w stages lines
-    // w, w + 4, ... of the chunk, each in segments of one DMA instruction
+    // w, w + NW, ... of the chunk, each in segments of one DMA instruction
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     float *dst = buf + wave * pitch + kLinePad + cl;
-    const int dst_step = kWaves * pitch;
+    const int dst_step = NW * pitch;
     if (rows && (n & 3) == 0) {
         const int S = (W + 255) >> 8;
         const int off = 4 * lane;
         const float *src = img + (size_t)(M0 + wave) * n + cl;
-        const size_t src_step = (size_t)kWaves * n;
-        for (int l = wave; l < Rc; l += kWaves, src += src_step, dst += dst_step)
+        const size_t src_step = (size_t)NW * n;
+        for (int l = wave; l < Rc; l += NW, src += src_step, dst += dst_step)
             for (int s = 0; s < S; s++) {
                 const int p = s << 8;
                 if (p + off < W)
@@ -221,10 +224,10 @@ __device__ __forceinline__ void stage_dma(float *buf, int pitch, const float *__
         const int S = (W + 63) >> 6;
         // rows: entry p of line l at img[(M0 + l) n + p]; columns: at img[p n + M0 + l]
         const float *src = rows ? img + (size_t)(M0 + wave) * n + cl : img + (size_t)cl * n + M0 + wave;
-        const size_t src_step = rows ? (size_t)kWaves * n : (size_t)kWaves;
+        const size_t src_step = rows ? (size_t)NW * n : (size_t)NW;
         const size_t lane_step = rows ? (size_t)lane : (size_t)lane * n;
         const size_t seg_step = rows ? (size_t)64 : (size_t)64 * n;
-        for (int l = wave; l < Rc; l += kWaves, src += src_step, dst += dst_step)
+        for (int l = wave; l < Rc; l += NW, src += src_step, dst += dst_step)
             for (int s = 0; s < S; s++) {
                 const int p = s << 6;
                 if (p + lane < W)
@@ -238,9 +241,10 @@ __device__ __forceinline__ void dma_wait() { __builtin_amdgcn_s_waitcnt(0); }
 
 // Zeroes the lines [Rc, R) of a staging buffer: a partial last chunk leaves
 // them unstaged, and whole-unit marches read them (they must add nothing).
+template <int NW>
 __device__ __forceinline__ void zero_tail(float *buf, int pitch, int R, int Rc)
 {
-    for (int e = Rc * pitch + threadIdx.x; e < R * pitch; e += kBlock) buf[e] = 0.0f;
+    for (int e = Rc * pitch + threadIdx.x; e < R * pitch; e += 64 * NW) buf[e] = 0.0f;
 }
 
 // ---------------------------------------------------------------------------
@@ -252,14 +256,15 @@ __device__ __forceinline__ void zero_tail(float *buf, int pitch, int R, int Rc)
 //   j1 -+ 2 lie at least 3/2 away, so the three taps j1-1, j1, j1+1 cover
 //   them: weights 1 - w (1 + g), 1 - w |g|, 1 - w (1 - g), clamped at 0.
 // ---------------------------------------------------------------------------
-template <int KIND, int RPT, int U, typename OUT>
+template <int KIND, int RPT, int U, typename OUT, int NW>
 __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float *lds)
 {
+    constexpr int kBlock = 64 * NW, kWaves = NW;
     // Lowest tap entry read: j0 for the forward walk, j1 - 1 for B^T; taps
     // below -kLinePad (and above n + 1) are clamped onto the zero borders.
     constexpr int kBias = KIND == kFwd ? kLinePad : kLinePad - 1;
     __shared__ AngleRow ang[kMaxG];
-    __shared__ int wrange[2][kWaves];
+    __shared__ int wrange[2][kMaxWaves];
 
     const float *__restrict__ x = J.x;
     const float *__restrict__ xT = J.xT;
@@ -375,8 +380,8 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
                 const int M0 = c_first * R, Rc = min(R, n - M0);
                 int cl, W;
                 chunk_span(span, gcount, M0, Rc, n, cl, W);
-                zero_tail(lds, pitch, R, Rc);
-                stage_dma(lds, pitch, src, n, dma_rows, M0, Rc, cl, W);
+                zero_tail<NW>(lds, pitch, R, Rc);
+                stage_dma<NW>(lds, pitch, src, n, dma_rows, M0, Rc, cl, W);
                 dma_wait();
             }
             __syncthreads();
@@ -388,8 +393,8 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
                     int cl, W;
                     chunk_span(span, gcount, M1, Rc1, n, cl, W);
                     float *nb = lds + (cur ^ 1) * buf_stride;
-                    zero_tail(nb, pitch, R, Rc1);
-                    stage_dma(nb, pitch, src, n, dma_rows, M1, Rc1, cl, W);
+                    zero_tail<NW>(nb, pitch, R, Rc1);
+                    stage_dma<NW>(nb, pitch, src, n, dma_rows, M1, Rc1, cl, W);
                 }
                 const float *chunk = lds + cur * buf_stride;
                 // units of this chunk that the wave marches (M0 and ulo are multiples of U)
@@ -467,44 +472,53 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
     }
 }
 
-template <int KIND, int RPT, int U, typename OUT>
-__global__ void __launch_bounds__(kBlock) k_ray(const JobList<RayJob> L)
+template <int KIND, int RPT, int U, typename OUT, int NW>
+__global__ void __launch_bounds__(64 * NW) k_ray(const JobList<RayJob> L)
 {
     extern __shared__ __align__(16) float lds[];
-    for_each_item(L, [&](const RayJob &J, long long item) { ray_item<KIND, RPT, U, OUT>(J, item, lds); });
+    for_each_item(L, [&](const RayJob &J, long long item) { ray_item<KIND, RPT, U, OUT, NW>(J, item, lds); });
 }
 
-template <int KIND, int RPT, int U, typename OUT>
+template <int KIND, int RPT, int U, typename OUT, int NW>
 int ray_launch1(size_t shm, const JobList<RayJob> &L, hipStream_t st)
 {
-    const long long grid = launch_grid(L, reinterpret_cast<const void *>(&k_ray<KIND, RPT, U, OUT>), kBlock, shm);
+    const long long grid =
+        launch_grid(L, reinterpret_cast<const void *>(&k_ray<KIND, RPT, U, OUT, NW>), 64 * NW, shm);
     if (grid <= 0 || grid > 0x7fffffffLL) return SKEI_ERANGE;
-    hipLaunchKernelGGL((k_ray<KIND, RPT, U, OUT>), dim3((unsigned)grid), dim3(kBlock), shm, st, L);
+    hipLaunchKernelGGL((k_ray<KIND, RPT, U, OUT, NW>), dim3((unsigned)grid), dim3(64 * NW), shm, st, L);
     return check_launch();
 }
 
-template <int KIND, int U, typename OUT>
+template <int KIND, int U, typename OUT, int NW>
 int ray_launch_u(int rpt, size_t shm, const JobList<RayJob> &L, hipStream_t st)
 {
     switch (rpt) {
-    case 1: return ray_launch1<KIND, 1, U, OUT>(shm, L, st);
-    case 2: return ray_launch1<KIND, 2, U, OUT>(shm, L, st);
-    case 3: return ray_launch1<KIND, 3, U, OUT>(shm, L, st);
-    case 4: return ray_launch1<KIND, 4, U, OUT>(shm, L, st);
+    case 1: return ray_launch1<KIND, 1, U, OUT, NW>(shm, L, st);
+    case 2: return ray_launch1<KIND, 2, U, OUT, NW>(shm, L, st);
+    case 3: return ray_launch1<KIND, 3, U, OUT, NW>(shm, L, st);
+    case 4: return ray_launch1<KIND, 4, U, OUT, NW>(shm, L, st);
+    default: return SKEI_ERANGE;
+    }
+}
+
+template <int KIND, typename OUT, int NW>
+int ray_launch_w(int rpt, int unroll, size_t shm, const JobList<RayJob> &L, hipStream_t st)
+{
+    switch (unroll) {
+    case 16: return ray_launch_u<KIND, 16, OUT, NW>(rpt, shm, L, st);
+    case 8: return ray_launch_u<KIND, 8, OUT, NW>(rpt, shm, L, st);
+    case 4: return ray_launch_u<KIND, 4, OUT, NW>(rpt, shm, L, st);
     default: return SKEI_ERANGE;
     }
 }
 
 template <int KIND, typename OUT>
-int ray_launch(int rpt, int unroll, size_t shm, const JobList<RayJob> &L, hipStream_t st)
+int ray_launch(const RayShape &sh, const JobList<RayJob> &L, hipStream_t st)
 {
     if (L.total <= 0) return SKEI_OK;
-    switch (unroll) {
-    case 16: return ray_launch_u<KIND, 16, OUT>(rpt, shm, L, st);
-    case 8: return ray_launch_u<KIND, 8, OUT>(rpt, shm, L, st);
-    case 4: return ray_launch_u<KIND, 4, OUT>(rpt, shm, L, st);
-    default: return SKEI_ERANGE;
-    }
+    if (sh.waves == 3) return ray_launch_w<KIND, OUT, 3>(sh.rpt, sh.unroll, sh.shm, L, st);
+    if (sh.waves == 4) return ray_launch_w<KIND, OUT, 4>(sh.rpt, sh.unroll, sh.shm, L, st);
+    return SKEI_ERANGE;
 }
 
 }  // namespace
@@ -512,9 +526,8 @@ int ray_launch(int rpt, int unroll, size_t shm, const JobList<RayJob> &L, hipStr
 int ray_run(int kind, bool out_double, const RayShape &sh, const JobList<RayJob> &L, hipStream_t st)
 {
     if (sh.shm > kLdsMax) return SKEI_ERANGE;
-    if (kind == kRayFwd) return out_double ? SKEI_EINVAL : ray_launch<kFwd, float>(sh.rpt, sh.unroll, sh.shm, L, st);
-    return out_double ? ray_launch<kBpT, double>(sh.rpt, sh.unroll, sh.shm, L, st)
-                      : ray_launch<kBpT, float>(sh.rpt, sh.unroll, sh.shm, L, st);
+    if (kind == kRayFwd) return out_double ? SKEI_EINVAL : ray_launch<kFwd, float>(sh, L, st);
+    return out_double ? ray_launch<kBpT, double>(sh, L, st) : ray_launch<kBpT, float>(sh, L, st);
 }
 
 int launch_radon_fwd(const skei_geom *g, const float *x, const float *xT, int batch, const int32_t *idx, int m,

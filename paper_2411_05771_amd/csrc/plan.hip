@@ -39,7 +39,7 @@ struct StageTable {
     long long grid_static = 0;
     size_t off_jobs = 0, off_first = 0, off_xr = 0;
     // launch parameters
-    RayShape ray{0, 16, 0};   // ray stages
+    RayShape ray{0, 16, 0, 0};   // ray stages (merged over the problems)
     size_t shm = 0;           // ramp stages
     int ga = 0;        // gather stages
     int ramp_block = 0;
@@ -111,14 +111,16 @@ int plan_build(skei_ei_plan *P)
     int max_nd = 1;
     for (const skei_ei_problem &p : P->probs) max_nd = std::max(max_nd, p.geom->n_det);
     const int def_rpt = max_nd > 400 ? 3 : 2;
-    // ray-stage shape code: rays per thread + 100 x chunk height
+    // ray-stage shape code: rays per thread + 100 x chunk height (+ 10000 for
+    // three-wave workgroups)
     // (B_S^T, with three taps per line, runs best with the higher occupancy
     // of 8-line chunks by default)
     auto choice = [&](int shape, int def_lines) {
         RayChoice c;
         c.own = false;
         c.rpt = shape % 100 > 0 ? shape % 100 : def_rpt;
-        c.lines = shape > 0 ? shape / 100 : def_lines;
+        c.lines = shape % 10000 > 0 ? shape % 10000 / 100 : def_lines;
+        c.waves = shape >= 10000 ? 3 : 4;
         return c;
     };
     const RayChoice fwd_c = choice(P->cfg[SKEI_STAGE_FWD].shape, 0);
@@ -413,8 +415,9 @@ int skei_ei_plan_configure(skei_ei_plan *plan, int stage, int dispatch, int shap
     if (!plan || stage < 0 || stage >= kStages) return SKEI_EINVAL;
     if (dispatch != SKEI_DISPATCH_PERSISTENT && dispatch != SKEI_DISPATCH_STATIC) return SKEI_EINVAL;
     if (is_ray_stage(stage)) {
-        const int rpt = shape % 100, lines = shape / 100;
-        if (shape < 0 || rpt > 4 || !(lines == 0 || lines == 4 || lines == 8 || lines == 16)) return SKEI_EINVAL;
+        const int rpt = shape % 100, lines = shape % 10000 / 100;
+        if (shape < 0 || shape >= 20000 || rpt > 4 || !(lines == 0 || lines == 4 || lines == 8 || lines == 16))
+            return SKEI_EINVAL;
     }
     if (is_gather_stage(stage) && !(shape == 0 || shape == 1 || shape == 2 || shape == 4 || shape == 14 ||
                                      shape == 24 || shape == 44))
@@ -440,8 +443,9 @@ int skei_ei_plan_get_config(const skei_ei_plan *plan, int stage, int *dispatch, 
     if (dispatch) *dispatch = plan->cfg[stage].dispatch;
     if (shape) {
         const StageTable &t = plan->tab[stage];
-        *shape = is_ray_stage(stage) ? t.ray.rpt + 100 * (plan->cfg[stage].shape / 100)
-                                     : is_gather_stage(stage) ? t.ga : 0;
+        *shape = is_ray_stage(stage)
+                     ? t.ray.rpt + 100 * (plan->cfg[stage].shape % 10000 / 100) + (t.ray.waves == 3 ? 10000 : 0)
+                     : is_gather_stage(stage) ? t.ga : 0;
     }
     return SKEI_OK;
 }
@@ -467,7 +471,7 @@ int skei_ei_plan_autotune(skei_ei_plan *plan, void *stream, int reps, const char
             continue;
         }
         std::vector<int> shapes{0};
-        if (is_ray_stage(s)) shapes = {1, 2, 3, 4, 802, 803, 402, 403};
+        if (is_ray_stage(s)) shapes = {1, 2, 3, 4, 802, 803, 402, 403, 10002, 10802, 10003, 10004, 10803};
         if (is_gather_stage(s)) shapes = {1, 2, 4, 14, 24, 44};
         float best_ms = 3.0e38f;
         best = plan->cfg[s];

@@ -247,6 +247,7 @@ enum GatherKind : int { kGatherJosephAdj = 0, kGatherBackproject = 1 };
 struct RayShape {
     int rpt;
     int unroll;
+    int waves;   // per workgroup: 3 or 4
     size_t shm;
 };
 
@@ -256,6 +257,8 @@ inline RayShape merge_shapes(const RayShape &a, const RayShape &b)
     RayShape r;
     r.rpt = a.rpt > b.rpt ? a.rpt : b.rpt;
     r.unroll = a.unroll < b.unroll ? a.unroll : b.unroll;   // units nest: 4 | 8 | 16
+    // jobs of a launch share the wave count (0 = unset; a mismatch fails the launch)
+    r.waves = a.waves == 0 ? b.waves : b.waves == 0 ? a.waves : a.waves == b.waves ? a.waves : -1;
     r.shm = a.shm > b.shm ? a.shm : b.shm;
     return r;
 }
@@ -277,6 +280,7 @@ int reduce_run(const JobList<RedJob> &L, hipStream_t st);
 //   split: detector segments per angle
 struct RayTune {
     int group = 0, lines = 0, split = 0;
+    int waves = 0;   // waves per workgroup (3 or 4; 0 = 4)
 };
 
 // Ray job of one operator application and the launch shape it needs.
