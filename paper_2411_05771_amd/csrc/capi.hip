@@ -150,6 +150,7 @@ int ei_problem_jobs(const skei_ei_problem &p, const EiBuffers &b, const RayChoic
     if ((rc = make_ray_job(g, b.z, b.zT, bc, p.angle_idx, m, b.ys, nullptr, tf, fwd.rpt, J.fwd[0],
                            J.fwd_shape[0])))
         return rc;
+    tf.waves = J.fwd_shape[0].waves;   // both jobs of the launch share the workgroup size
     if ((rc = make_ray_job(g, p.x, b.xT, batch, p.mc_idx, m_mc, b.rmc, p.y, tf, fwd.rpt, J.fwd[1],
                            J.fwd_shape[1])))
         return rc;

@@ -56,27 +56,39 @@ int make_ray_job(const skei_geom *g, const float *x, const float *xT, int batch,
 {
     const int n = g->n, nd = g->n_det;
     const long long base_items = (long long)batch * m;
-    const int waves = t.waves == 3 ? 3 : 4;
-    const int block = 64 * waves;
-    const int cap = (rpt_cap > 0 ? std::min(rpt_cap, kMaxRpt) : kMaxRpt) * block;
-    int nseg = t.split > 0 ? t.split
-                           : rpt_cap > 0 ? (nd + cap - 1) / cap
-                                         : ((base_items < 512 && nd >= 128) ? 2 : 1);
-    nseg = std::max(1, std::min(nseg, nd));
-    int G;
-    if (t.group > 0)
-        G = t.group;
-    else
-        G = std::max(1, (rpt_cap > 0 ? cap : 2 * block) / ((nd + nseg - 1) / nseg));
-    G = std::max(1, std::min(std::min(G, kMaxG), m));
-    for (;;) {
-        const int seg = (nd + nseg - 1) / nseg;
-        if ((long long)G * seg <= cap) break;
-        if (G > 1)
-            G--;
-        else
-            nseg++;
+    // listed angles per item (G) and detector segments (nseg) for workgroups
+    // of `w` waves; returns the fraction of ray slots that hold a ray
+    auto layout = [&](int w, int &G, int &nseg) {
+        const int block = 64 * w;
+        const int cap = (rpt_cap > 0 ? std::min(rpt_cap, kMaxRpt) : kMaxRpt) * block;
+        nseg = t.split > 0 ? t.split
+                           : rpt_cap > 0 ? (nd + cap - 1) / cap : ((base_items < 512 && nd >= 128) ? 2 : 1);
+        nseg = std::max(1, std::min(nseg, nd));
+        G = t.group > 0 ? t.group : std::max(1, (rpt_cap > 0 ? cap : 2 * block) / ((nd + nseg - 1) / nseg));
+        G = std::max(1, std::min(std::min(G, kMaxG), m));
+        for (;;) {
+            const int seg = (nd + nseg - 1) / nseg;
+            if ((long long)G * seg <= cap) break;
+            if (G > 1)
+                G--;
+            else
+                nseg++;
+        }
+        const int rays = G * ((nd + nseg - 1) / nseg);
+        return (double)rays / (double)(((rays + block - 1) / block) * block);
+    };
+    int G, nseg, waves = t.waves == 3 ? 3 : 4;
+    double fill = layout(waves, G, nseg);
+    if (t.waves == 0) {
+        // automatic: three waves when they leave fewer ray slots empty
+        int G3, nseg3;
+        if (layout(3, G3, nseg3) > fill + 0.05) {
+            waves = 3;
+            G = G3;
+            nseg = nseg3;
+        }
     }
+    const int block = 64 * waves;
     J = RayJob{};
     J.x = x;
     J.xT = xT;
