@@ -85,7 +85,8 @@ int skei_geom_info(const skei_geom *g, int *n, int *n_angles, int *n_det);
 
 /* Launch shape of the ray-driven kernels (forward projector, B_S^T) used by
  * later calls on this geometry: `group` listed angles per workgroup (1..8),
- * `lines` image lines per LDS chunk, `split` detector segments per angle;
+ * `lines` image lines per march unit (an LDS chunk holds two), `split`
+ * detector segments per angle;
  * 0 keeps the built-in choice.  Results do not depend on these (bitwise);
  * only speed does.  Not to be changed while calls on the geometry run. */
 enum { SKEI_OP_FWD = 0, SKEI_OP_BPT = 1 };
@@ -225,8 +226,9 @@ int skei_ei_plan_run(skei_ei_plan *plan, void *stream);
  *     items from per-XCD queues, then steal from the other XCDs' queues;
  *   SKEI_DISPATCH_STATIC: one workgroup per work item, XCD-major ranges.
  * `shape`: for the ray-driven stages (FWD, BP_T) rays per thread (1..4)
- * plus 100 x the image lines per LDS chunk (0 = built-in, 4, 8 or 16), plus
- * 10000 for workgroups of three waves instead of four;
+ * plus 100 x the image lines per march unit (0 = built-in, 4, 8 or 16; an
+ * LDS chunk holds two units), plus 10000 for workgroups of three waves
+ * instead of four;
  * for the gathers (BP_RESID, ADJ) angle groups per pixel (1, 2, 4) with one
  * pixel per thread, or 10 x groups + 4 (14, 24, 44) with four pixels per
  * thread; 0 keeps the default; ignored by the other stages.  Synchronises the device when

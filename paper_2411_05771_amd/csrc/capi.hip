@@ -136,7 +136,9 @@ int ei_problem_jobs(const skei_ei_problem &p, const EiBuffers &b, const RayChoic
     J.rot[0] = make_rot_job(p.x, batch, copies, n, p.cos_sin, b.z, b.zT);
     J.rot[1] = make_rot_job(p.x, batch, 1, n, nullptr, nullptr, b.xT);
     RayTune tf = g->tune_fwd, tb = g->tune_bpt;
-    if (tb.lines == 0) tb.lines = 8;   // B_S^T's built-in chunk height (higher occupancy)
+    // built-in chunk height of both ray stages: 8 lines (higher occupancy)
+    if (tf.lines == 0) tf.lines = 8;
+    if (tb.lines == 0) tb.lines = 8;
     if (!fwd.own) {
         tf = RayTune{};
         tf.lines = fwd.lines;

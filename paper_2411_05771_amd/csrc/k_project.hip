@@ -12,10 +12,12 @@
 // Staging uses the LDS DMA path (global_load_lds): each wave instruction
 // moves a contiguous run of a line straight from global memory into LDS, no
 // registers involved -- 16-byte lanes along image rows, 4-byte lanes gathering
-// a column (which lands transposed, i.e. line-contiguous, in LDS).  Two LDS
-// buffers alternate: the DMA of chunk c+1 is in flight while chunk c is
-// marched.  Only the span of each line that the group's rays can touch is
-// staged.
+// a column (which lands transposed, i.e. line-contiguous, in LDS).  One
+// buffer of two march units' height is staged, then marched; the DMA latency
+// is covered by the other workgroups of the CU (two alternating half-height
+// buffers measured slower: their per-chunk bookkeeping costs more than the
+// latency they hide).  Only the span of each line that the group's rays can
+// touch is staged.
 //
 // Ray positions are 32.32 fixed-point numbers stepped by exact integer adds
 // (u(k, M+1) = u(k, M) + du), so the interpolation position carries no
@@ -40,7 +42,7 @@ typedef __attribute__((address_space(3))) void lmem_t;
 constexpr int kMaxWaves = 4;                 // waves per workgroup: 3 or 4
 constexpr int kMaxG = 8;                     // listed angles per workgroup
 constexpr int kMaxRpt = 4;                   // rays per thread
-constexpr size_t kLdsBudget = 40 * 1024;     // both staging buffers (default)
+constexpr size_t kLdsBudget = 40 * 1024;     // staging buffer (default)
 constexpr size_t kLdsMax = 160 * 1024;       // LDS of one CU (gfx950)
 constexpr float kTwoM32 = 2.3283064365386963e-10f;   // 2^-32
 
@@ -106,27 +108,30 @@ int make_ray_job(const skei_geom *g, const float *x, const float *xT, int batch,
     J.ngroups = (m + G - 1) / G;
     J.pitch = line_pitch(n);
     // lines per unrolled march unit: the largest of 16, 8, 4 whose two
-    // staging buffers fit the LDS budget (4 always fits within 64 KB)
+    // two-unit staging buffer fits the LDS budget (4 always fits in 64 KB)
     const size_t line_bytes = (size_t)J.pitch * sizeof(float);
     int U = 2 * 16 * line_bytes <= kLdsBudget ? 16 : 2 * 8 * line_bytes <= kLdsBudget ? 8 : 4;
     size_t budget = std::max(kLdsBudget, 2 * (size_t)U * line_bytes);
     if (t.lines > 0) {
         // a requested chunk height sets the unit (16, 8 or 4 lines) and may
-        // spend up to the whole LDS of a CU on the two buffers
+        // spend up to the whole LDS of a CU on the buffer
         U = t.lines >= 16 ? 16 : t.lines >= 8 ? 8 : 4;
         budget = std::min(kLdsMax, std::max(2 * (size_t)U * line_bytes, 2 * (size_t)t.lines * line_bytes));
         if (2 * (size_t)U * line_bytes > budget) return SKEI_ERANGE;
     }
     int R = (int)(budget / (2 * line_bytes));
     R = std::min(R, t.lines > 0 ? t.lines : 64);
-    R = std::max(U, R / U * U);   // whole units per chunk
-    J.R = R;
+    R = std::max(U, R / U * U);   // whole units per half
+    // one staging buffer of 2R lines (whole units): staged, then marched --
+    // measured ahead of two alternating R-line buffers, whose per-chunk
+    // bookkeeping costs more than the DMA latency they hide
+    J.R = 2 * R;
     shape.unroll = U;
     J.resid = yfull != nullptr;
     J.items = (long long)batch * J.ngroups * J.nseg;
     shape.rpt = (G * J.seg + block - 1) / block;
     shape.waves = waves;
-    shape.shm = 2 * (size_t)R * J.pitch * sizeof(float);
+    shape.shm = (size_t)J.R * J.pitch * sizeof(float);
     if (shape.shm > kLdsMax || shape.rpt > kMaxRpt) return SKEI_ERANGE;
     return SKEI_OK;
 }
@@ -295,19 +300,18 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
     const int k_begin = sg * seg, k_len = min(seg, n_det - k_begin);
     const int tid = threadIdx.x;
     if (tid < gcount) ang[tid] = tab[idx[r0 + tid]];
-    // Zero the pads of every line of both buffers: the DMA never writes them,
+    // Zero the pads of every line of the buffer: the DMA never writes them,
     // and clamped taps read them.  Entries of [0, n) outside a chunk's staged
     // span are never read (the span covers every tap of the group's rays).
     {
         const int padw = pitch - n;   // kLinePad before the line, the rest after it
-        for (int e = tid; e < 2 * R * padw; e += kBlock) {
+        for (int e = tid; e < R * padw; e += kBlock) {
             const int l = e / padw, k = e - l * padw;
             lds[l * pitch + (k < kLinePad ? k : n + k)] = 0.0f;
         }
     }
     __syncthreads();
     const float *img = x + (size_t)b * n * n;
-    const int buf_stride = R * pitch;
 
     // Ray slot of (thread, q): blocks of 32 consecutive detectors are dealt
     // round-robin to the waves, so every wave spans the whole detector range
@@ -388,27 +392,17 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
         const unsigned cap = (unsigned)(n + 1 + kBias);
         if (blo <= bhi) {
             const int c_first = blo / R, c_last = bhi / R;
-            {
-                const int M0 = c_first * R, Rc = min(R, n - M0);
-                int cl, W;
-                chunk_span(span, gcount, M0, Rc, n, cl, W);
-                zero_tail<NW>(lds, pitch, R, Rc);
-                stage_dma<NW>(lds, pitch, src, n, dma_rows, M0, Rc, cl, W);
-                dma_wait();
-            }
-            __syncthreads();
-            int cur = 0;
             for (int c = c_first; c <= c_last; c++) {
                 const int M0 = c * R, Rc = min(R, n - M0);
-                if (c < c_last) {                 // next chunk streams in while this one is marched
-                    const int M1 = M0 + R, Rc1 = min(R, n - M1);
+                {
                     int cl, W;
-                    chunk_span(span, gcount, M1, Rc1, n, cl, W);
-                    float *nb = lds + (cur ^ 1) * buf_stride;
-                    zero_tail<NW>(nb, pitch, R, Rc1);
-                    stage_dma<NW>(nb, pitch, src, n, dma_rows, M1, Rc1, cl, W);
+                    chunk_span(span, gcount, M0, Rc, n, cl, W);
+                    zero_tail<NW>(lds, pitch, R, Rc);
+                    stage_dma<NW>(lds, pitch, src, n, dma_rows, M0, Rc, cl, W);
+                    dma_wait();
                 }
-                const float *chunk = lds + cur * buf_stride;
+                __syncthreads();
+                const float *chunk = lds;
                 // units of this chunk that the wave marches (M0 and ulo are multiples of U)
                 const int ub = max(ulo, M0), ue = min(hi, M0 + Rc - 1);
                 for (int Mb = ub; Mb <= ue; Mb += U) {
@@ -452,9 +446,7 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
                         }
                     }
                 }
-                dma_wait();
-                __syncthreads();
-                cur ^= 1;
+                __syncthreads();   // the chunk is marched before the next one lands
             }
         } else {
             __syncthreads();

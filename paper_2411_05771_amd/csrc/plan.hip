@@ -113,18 +113,18 @@ int plan_build(skei_ei_plan *P)
     const int def_rpt = max_nd > 400 ? 3 : 2;
     // ray-stage shape code: rays per thread + 100 x chunk height (+ 10000 for
     // three-wave workgroups)
-    // (B_S^T, with three taps per line, runs best with the higher occupancy
-    // of 8-line chunks by default)
+    // (both run best with the higher occupancy of 8-line chunks by default;
+    // the default wave count is the first problem's automatic choice)
     auto choice = [&](int shape, int def_lines) {
         RayChoice c;
         c.own = false;
         c.rpt = shape % 100 > 0 ? shape % 100 : def_rpt;
         c.lines = shape % 10000 > 0 ? shape % 10000 / 100 : def_lines;
-        c.waves = shape >= 10000 ? 3 : 4;
+        c.waves = shape >= 10000 ? 3 : shape > 0 ? 4 : 0;
         return c;
     };
-    const RayChoice fwd_c = choice(P->cfg[SKEI_STAGE_FWD].shape, 0);
-    const RayChoice bpt_c = choice(P->cfg[SKEI_STAGE_BP_T].shape, 8);
+    RayChoice fwd_c = choice(P->cfg[SKEI_STAGE_FWD].shape, 8);
+    RayChoice bpt_c = choice(P->cfg[SKEI_STAGE_BP_T].shape, 8);
     std::vector<RotJob> rot;
     std::vector<RayJob> fwd, bpt;
     std::vector<RampJob> ramp, rampT;
@@ -138,6 +138,9 @@ int plan_build(skei_ei_plan *P)
         EiJobs J;
         int rc = ei_problem_jobs(p, P->bufs[i], fwd_c, bpt_c, J);
         if (rc) return rc;
+        // an automatic wave count is fixed by the first problem for all
+        if (fwd_c.waves == 0) fwd_c.waves = J.fwd_shape[0].waves;
+        if (bpt_c.waves == 0 && J.grad) bpt_c.waves = J.bpt_shape.waves;
         rot.push_back(J.rot[0]);
         rot.push_back(J.rot[1]);
         fwd.push_back(J.fwd[0]);

@@ -276,7 +276,7 @@ int reduce_run(const JobList<RedJob> &L, hipStream_t st);
 
 // Launch shape of the ray-driven kernels (0 = automatic choice):
 //   group: listed angles per workgroup (they share every staged image chunk)
-//   lines: image lines per LDS chunk
+//   lines: image lines per march unit (an LDS chunk holds two)
 //   split: detector segments per angle
 struct RayTune {
     int group = 0, lines = 0, split = 0;
