@@ -228,7 +228,7 @@ int skei_ei_plan_run(skei_ei_plan *plan, void *stream);
  * `shape`: for the ray-driven stages (FWD, BP_T) rays per thread (1..4)
  * plus 100 x the image lines per march unit (0 = built-in, 4, 8 or 16; an
  * LDS chunk holds two units), plus 10000 for workgroups of three waves
- * instead of four;
+ * instead of four, plus 20000 for LDS chunks of four units;
  * for the gathers (BP_RESID, ADJ) angle groups per pixel (1, 2, 4) with one
  * pixel per thread, or 10 x groups + 4 (14, 24, 44) with four pixels per
  * thread; 0 keeps the default; ignored by the other stages.  Synchronises the device when

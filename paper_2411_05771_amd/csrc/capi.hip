@@ -143,11 +143,13 @@ int ei_problem_jobs(const skei_ei_problem &p, const EiBuffers &b, const RayChoic
         tf = RayTune{};
         tf.lines = fwd.lines;
         tf.waves = fwd.waves;
+        tf.units = fwd.units;
     }
     if (!bpt.own) {
         tb = RayTune{};
         tb.lines = bpt.lines;
         tb.waves = bpt.waves;
+        tb.units = bpt.units;
     }
     if ((rc = make_ray_job(g, b.z, b.zT, bc, p.angle_idx, m, b.ys, nullptr, tf, fwd.rpt, J.fwd[0],
                            J.fwd_shape[0])))

@@ -43,10 +43,10 @@ struct EiJobs {
 };
 
 // Launch shape of a ray stage's jobs: rays-per-thread cap (0 = per-problem
-// automatic shape), chunk height (0 = the built-in choice) and waves per
-// workgroup.  `own` = use the geometry's tuning (skei_geom_set_tuning) instead.
+// automatic shape), march unit height (0 = the built-in choice), waves per
+// workgroup and units per LDS chunk.  `own` = use the geometry's tuning (skei_geom_set_tuning) instead.
 struct RayChoice {
-    int rpt = 0, lines = 0, waves = 4;
+    int rpt = 0, lines = 0, waves = 4, units = 2;
     bool own = true;
 };
 int ei_problem_jobs(const skei_ei_problem &p, const EiBuffers &b, const RayChoice &fwd, const RayChoice &bpt,

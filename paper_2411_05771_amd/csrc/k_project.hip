@@ -122,10 +122,10 @@ int make_ray_job(const skei_geom *g, const float *x, const float *xT, int batch,
     int R = (int)(budget / (2 * line_bytes));
     R = std::min(R, t.lines > 0 ? t.lines : 64);
     R = std::max(U, R / U * U);   // whole units per half
-    // one staging buffer of 2R lines (whole units): staged, then marched --
-    // measured ahead of two alternating R-line buffers, whose per-chunk
-    // bookkeeping costs more than the DMA latency they hide
-    J.R = 2 * R;
+    // one staging buffer of 2R lines (whole units; 4R on request): staged,
+    // then marched -- measured ahead of two alternating R-line buffers, whose
+    // per-chunk bookkeeping costs more than the DMA latency they hide
+    J.R = (t.units == 4 ? 4 : 2) * R;
     shape.unroll = U;
     J.resid = yfull != nullptr;
     J.items = (long long)batch * J.ngroups * J.nseg;

@@ -111,8 +111,8 @@ int plan_build(skei_ei_plan *P)
     int max_nd = 1;
     for (const skei_ei_problem &p : P->probs) max_nd = std::max(max_nd, p.geom->n_det);
     const int def_rpt = max_nd > 400 ? 3 : 2;
-    // ray-stage shape code: rays per thread + 100 x chunk height (+ 10000 for
-    // three-wave workgroups)
+    // ray-stage shape code: rays per thread + 100 x march unit height, + 10000
+    // for three-wave workgroups, + 20000 for LDS chunks of four units
     // (both run best with the higher occupancy of 8-line chunks by default;
     // the default wave count is the first problem's automatic choice)
     auto choice = [&](int shape, int def_lines) {
@@ -120,7 +120,8 @@ int plan_build(skei_ei_plan *P)
         c.own = false;
         c.rpt = shape % 100 > 0 ? shape % 100 : def_rpt;
         c.lines = shape % 10000 > 0 ? shape % 10000 / 100 : def_lines;
-        c.waves = shape >= 10000 ? 3 : shape > 0 ? 4 : 0;
+        c.waves = (shape / 10000) & 1 ? 3 : shape > 0 ? 4 : 0;
+        c.units = shape >= 20000 ? 4 : 2;
         return c;
     };
     RayChoice fwd_c = choice(P->cfg[SKEI_STAGE_FWD].shape, 8);
@@ -419,7 +420,7 @@ int skei_ei_plan_configure(skei_ei_plan *plan, int stage, int dispatch, int shap
     if (dispatch != SKEI_DISPATCH_PERSISTENT && dispatch != SKEI_DISPATCH_STATIC) return SKEI_EINVAL;
     if (is_ray_stage(stage)) {
         const int rpt = shape % 100, lines = shape % 10000 / 100;
-        if (shape < 0 || shape >= 20000 || rpt > 4 || !(lines == 0 || lines == 4 || lines == 8 || lines == 16))
+        if (shape < 0 || shape >= 40000 || rpt > 4 || !(lines == 0 || lines == 4 || lines == 8 || lines == 16))
             return SKEI_EINVAL;
     }
     if (is_gather_stage(stage) && !(shape == 0 || shape == 1 || shape == 2 || shape == 4 || shape == 14 ||
@@ -447,7 +448,8 @@ int skei_ei_plan_get_config(const skei_ei_plan *plan, int stage, int *dispatch, 
     if (shape) {
         const StageTable &t = plan->tab[stage];
         *shape = is_ray_stage(stage)
-                     ? t.ray.rpt + 100 * (plan->cfg[stage].shape % 10000 / 100) + (t.ray.waves == 3 ? 10000 : 0)
+                     ? t.ray.rpt + 100 * (plan->cfg[stage].shape % 10000 / 100) + (t.ray.waves == 3 ? 10000 : 0) +
+                           (plan->cfg[stage].shape >= 20000 ? 20000 : 0)
                      : is_gather_stage(stage) ? t.ga : 0;
     }
     return SKEI_OK;
@@ -474,7 +476,8 @@ int skei_ei_plan_autotune(skei_ei_plan *plan, void *stream, int reps, const char
             continue;
         }
         std::vector<int> shapes{0};
-        if (is_ray_stage(s)) shapes = {1, 2, 3, 4, 802, 803, 402, 403, 10002, 10802, 10003, 10004, 10803};
+        if (is_ray_stage(s))
+            shapes = {1, 2, 3, 4, 802, 803, 402, 403, 10002, 10802, 10003, 10004, 10803, 30402, 30802, 20402, 20403};
         if (is_gather_stage(s)) shapes = {1, 2, 4, 14, 24, 44};
         float best_ms = 3.0e38f;
         best = plan->cfg[s];

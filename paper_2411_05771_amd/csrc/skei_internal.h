@@ -281,6 +281,7 @@ int reduce_run(const JobList<RedJob> &L, hipStream_t st);
 struct RayTune {
     int group = 0, lines = 0, split = 0;
     int waves = 0;   // waves per workgroup (3 or 4; 0 = whichever leaves fewer ray slots empty)
+    int units = 2;   // march units per LDS chunk (2 or 4)
 };
 
 // Ray job of one operator application and the launch shape it needs.
