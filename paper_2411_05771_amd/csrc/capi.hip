@@ -151,11 +151,17 @@ int ei_problem_jobs(const skei_ei_problem &p, const EiBuffers &b, const RayChoic
         tb.waves = bpt.waves;
         tb.units = bpt.units;
     }
-    if ((rc = make_ray_job(g, b.z, b.zT, bc, p.angle_idx, m, b.ys, nullptr, tf, fwd.rpt, J.fwd[0],
+    // Without a tuning of the geometry, the ray jobs take the plans' default
+    // rays per thread (one angle per item for N_det up to the slots): items
+    // holding several angles measured markedly slower than one-angle items.
+    const int def_rpt = g->n_det > 400 ? 3 : 2;
+    const int rpt_f = fwd.own && tf.group == 0 && tf.split == 0 ? def_rpt : fwd.rpt;
+    const int rpt_b = bpt.own && tb.group == 0 && tb.split == 0 ? def_rpt : bpt.rpt;
+    if ((rc = make_ray_job(g, b.z, b.zT, bc, p.angle_idx, m, b.ys, nullptr, tf, rpt_f, J.fwd[0],
                            J.fwd_shape[0])))
         return rc;
     tf.waves = J.fwd_shape[0].waves;   // both jobs of the launch share the workgroup size
-    if ((rc = make_ray_job(g, p.x, b.xT, batch, p.mc_idx, m_mc, b.rmc, p.y, tf, fwd.rpt, J.fwd[1],
+    if ((rc = make_ray_job(g, p.x, b.xT, batch, p.mc_idx, m_mc, b.rmc, p.y, tf, rpt_f, J.fwd[1],
                            J.fwd_shape[1])))
         return rc;
     // ||r_MC||^2 as row sums in a fixed order (in the ramp launch): the loss
@@ -177,7 +183,7 @@ int ei_problem_jobs(const skei_ei_problem &p, const EiBuffers &b, const RayChoic
     // backward: ysd = B_S^T r ; qs = (pi/m) H ysd ; z = r - A_S^T qs ;
     //           amc = A_mc^T r_MC ; grad = (2 lambda / C) sum_c T_c^T z - 2 amc
     J.grad = p.grad != nullptr;
-    if ((rc = make_ray_job(g, b.r, b.rT, bc, p.angle_idx, m, b.ysd, nullptr, tb, bpt.rpt, J.bpt,
+    if ((rc = make_ray_job(g, b.r, b.rT, bc, p.angle_idx, m, b.ysd, nullptr, tb, rpt_b, J.bpt,
                            J.bpt_shape)))
         return rc;
     J.rampT = make_ramp_job(g, b.ysd, (long long)bc * m, pim, b.qs);
