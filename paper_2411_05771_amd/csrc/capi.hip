@@ -348,13 +348,18 @@ int skei_ei_loss_grad(const skei_geom *g, const float *x, const float *y, int ba
     if ((rc = staged(SKEI_STAGE_BP_RESID, st,
                      [&] { return gather_run(kGatherBackproject, gather_groups_auto(m), inline_jobs(&J.bp, 1), st); })))
         return rc;
-    if ((rc = staged(SKEI_STAGE_REDUCE, st, [&] { return reduce_run(inline_jobs(&J.red, 1), st); }))) return rc;
+    // with a gradient, the loss is formed by one item of the RAMP_T launch
+    // (same fixed order) and REDUCE launches nothing
+    if ((rc = staged(SKEI_STAGE_REDUCE, st,
+                     [&] { return grad ? SKEI_OK : reduce_run(inline_jobs(&J.red, 1), st); })))
+        return rc;
     if (!grad) return SKEI_OK;
+    const RampJob rampT[2] = {make_loss_job(J.red), J.rampT};   // the loss item starts first
     if ((rc = staged(SKEI_STAGE_BP_T, st,
                      [&] { return ray_run(kRayBpT, true, J.bpt_shape, inline_jobs(&J.bpt, 1), st); })))
         return rc;
     if ((rc = staged(SKEI_STAGE_RAMP_T, st,
-                     [&] { return ramp_run(true, ramp_block(g->n_det), ramp_shm(g->n_det), inline_jobs(&J.rampT, 1), st); })))
+                     [&] { return ramp_run(true, ramp_block(g->n_det), ramp_shm(g->n_det), inline_jobs(rampT, 2), st); })))
         return rc;
     if ((rc = staged(SKEI_STAGE_ADJ, st, [&] {
              return gather_run(kGatherJosephAdj, gather_groups_auto(std::max(m, m_mc)), inline_jobs(J.adj, 2), st);

@@ -43,6 +43,10 @@ __device__ __forceinline__ void ramp_item(const RampJob &J, long long r, double 
     const int E = ramp_taps(n_det), ES = E / S;
     const int pad = ramp_pad(n_det);
     const int tid = threadIdx.x, bs = blockDim.x;
+    if (J.loss) {
+        fixed_order_loss(J.s0, J.n0, J.w0, J.s1, J.n1, J.w1, J.loss);
+        return;
+    }
     if (J.partial) {
         // row sums of squares, kRampSumRows rows per item: wave w takes row
         // kRampSumRows r + w, lane-strided then a butterfly, so the order does
@@ -177,6 +181,21 @@ RampJob make_row_sumsq_job(const skei_geom *g, const float *p, long long rows, d
     J.n_det = g->n_det;
     J.rows = rows;
     J.items = (rows + kRampSumRows - 1) / kRampSumRows;
+    return J;
+}
+
+RampJob make_loss_job(const RedJob &r)
+{
+    RampJob J{};
+    J.s0 = r.p0;
+    J.n0 = r.n0;
+    J.w0 = r.w0;
+    J.s1 = r.p1;
+    J.n1 = r.n1;
+    J.w1 = r.w1;
+    J.loss = r.out;
+    J.n_det = 1;
+    J.items = 1;
     return J;
 }
 

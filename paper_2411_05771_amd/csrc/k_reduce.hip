@@ -38,18 +38,10 @@ __global__ void __launch_bounds__(kRedBlock) k_sumsq(const float *__restrict__ a
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
+// The same fixed order as the loss items of the ramp launch (fixed_order_loss).
 __device__ __forceinline__ void reduce_item(const RedJob &J)
 {
-    __shared__ double sh[kRedBlock / 64];
-    double a0 = 0.0, a1 = 0.0;
-    for (long long i = threadIdx.x; i < J.n0; i += kRedBlock) a0 += J.p0[i];
-    if (J.p1)
-        for (long long i = threadIdx.x; i < J.n1; i += kRedBlock) a1 += J.p1[i];
-    __syncthreads();   // an earlier item of this workgroup may still read sh[]
-    const double s0 = block_sum(a0, sh);
-    __syncthreads();
-    const double s1 = block_sum(a1, sh);
-    if (threadIdx.x == 0) J.out[0] = J.w0 * s0 + (J.p1 ? J.w1 * s1 : 0.0);
+    fixed_order_loss(J.p0, J.n0, J.w0, J.p1, J.n1, J.w1, J.out);
 }
 
 __global__ void __launch_bounds__(kRedBlock) k_reduce2(const JobList<RedJob> L)

@@ -128,7 +128,7 @@ int plan_build(skei_ei_plan *P)
     RayChoice bpt_c = choice(P->cfg[SKEI_STAGE_BP_T].shape, 8);
     std::vector<RotJob> rot;
     std::vector<RayJob> fwd, bpt;
-    std::vector<RampJob> ramp, rampT;
+    std::vector<RampJob> ramp, rampT, loss;
     std::vector<GatherJob> bp, adj;
     std::vector<RedJob> red;
     std::vector<RotAdjJob> radj;
@@ -153,11 +153,12 @@ int plan_build(skei_ei_plan *P)
         ramp.push_back(J.ramp[1]);
         bp.push_back(J.bp);
         max_m_bp = std::max(max_m_bp, p.m);
-        red.push_back(J.red);
+        if (!J.grad) red.push_back(J.red);   // else the loss is an item of the RAMP_T launch
         if (J.grad) {
             bpt.push_back(J.bpt);
             t[SKEI_STAGE_BP_T].ray = merge_shapes(t[SKEI_STAGE_BP_T].ray, J.bpt_shape);
             rampT.push_back(J.rampT);
+            loss.push_back(make_loss_job(J.red));
             adj.push_back(J.adj[0]);
             adj.push_back(J.adj[1]);
             max_m_adj = std::max(max_m_adj, std::max(p.m, p.m_mc));
@@ -181,6 +182,7 @@ int plan_build(skei_ei_plan *P)
     lay_out(bp, t[SKEI_STAGE_BP_RESID], img);
     lay_out(red, t[SKEI_STAGE_REDUCE], img);
     lay_out(bpt, t[SKEI_STAGE_BP_T], img);
+    rampT.insert(rampT.begin(), loss.begin(), loss.end());   // the loss items start first
     lay_out(rampT, t[SKEI_STAGE_RAMP_T], img);
     lay_out(adj, t[SKEI_STAGE_ADJ], img);
     lay_out(radj, t[SKEI_STAGE_ROTATE_ADJ], img);

@@ -93,7 +93,9 @@ struct GatherJob {
 
 // Ram-Lak filter along detector rows: q = scale * H p.  An item is one row.
 // With `partial` set the job instead sums the squares of each row of p:
-// partial[row] = sum_k p[row][k]^2, in double, in a fixed order.
+// partial[row] = sum_k p[row][k]^2, in double, in a fixed order.  With `loss`
+// set it is one item that forms the EI loss from the partial sums (see
+// fixed_order_loss): loss = w0 * sum(s0[0..n0)) + w1 * sum(s1[0..n1)).
 struct RampJob {
     const void *p;           // float or double, by launch
     float *q;
@@ -103,6 +105,10 @@ struct RampJob {
     float scale;
     long long rows;          // rows of a sum-of-squares job
     long long items;
+    const double *s0, *s1;   // loss job
+    long long n0, n1;
+    double w0, w1;
+    double *loss;
 };
 
 // out[b][c] = T_c x[b] (and outT = its transpose), or, with cs == nullptr, the
@@ -179,7 +185,10 @@ struct JobList {
 // used to cut work lists into XCD ranges of about equal cost.
 inline double item_cost(const RayJob &j) { return (double)j.G * j.seg * j.n + 4.0 * j.n * j.n / (j.R > 0 ? j.R : 1); }
 inline double item_cost(const GatherJob &j) { return 256.0 * (j.m + 8); }
-inline double item_cost(const RampJob &j) { return j.partial ? 4.0 * j.n_det : (double)j.n_det * (j.n_det / 2 + 4); }
+inline double item_cost(const RampJob &j)
+{
+    return j.loss ? (double)(j.n0 + j.n1) : j.partial ? 4.0 * j.n_det : (double)j.n_det * (j.n_det / 2 + 4);
+}
 inline double item_cost(const RotJob &j) { return j.cs ? 256.0 * 4 : 256.0; }
 inline double item_cost(const RotAdjJob &j) { return 64.0 * 9 * j.copies; }
 inline double item_cost(const RedJob &j) { return (double)(j.n0 + j.n1); }
@@ -299,6 +308,8 @@ int gather_groups_auto(int m);   // default GA for m listed angles
 RampJob make_ramp_job(const struct ::skei_geom *g, const void *p, long long rows, float scale, float *q);
 // Row sums of squares of p [rows][N_det] (float) into partial[rows]; runs in a ramp launch.
 RampJob make_row_sumsq_job(const struct ::skei_geom *g, const float *p, long long rows, double *partial);
+// The EI loss from its partial sums, as one item of a ramp launch.
+RampJob make_loss_job(const RedJob &r);
 int ramp_block(int n_det);      // threads per row
 size_t ramp_shm(int n_det);     // LDS bytes per row
 

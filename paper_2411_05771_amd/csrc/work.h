@@ -119,6 +119,38 @@ __device__ __forceinline__ void for_each_item(const JobList<Job> &L, Body &&body
     }
 }
 
+// out = w0 * sum(p0[0..n0)) + w1 * sum(p1[0..n1)) (p1 may be null), by the
+// first 256 threads of the workgroup (blockDim.x >= 256): thread-strided
+// sums, a butterfly per wave, then the four wave sums in a fixed order -- the
+// same order whatever kernel or block size runs it.  Every thread calls it.
+__device__ __forceinline__ void fixed_order_loss(const double *p0, long long n0, double w0, const double *p1,
+                                                 long long n1, double w1, double *out)
+{
+    __shared__ double wave_part[2][4];
+    const int t = threadIdx.x;
+    if (t < 256) {
+        double a = 0.0, e = 0.0;
+        for (long long i = t; i < n0; i += 256) a += p0[i];
+        if (p1)
+            for (long long i = t; i < n1; i += 256) e += p1[i];
+        for (int o = 32; o > 0; o >>= 1) {
+            a += __shfl_xor(a, o);
+            e += __shfl_xor(e, o);
+        }
+        if ((t & 63) == 0) {
+            wave_part[0][t >> 6] = a;
+            wave_part[1][t >> 6] = e;
+        }
+    }
+    __syncthreads();
+    if (t == 0) {
+        const double a = (wave_part[0][0] + wave_part[0][1]) + (wave_part[0][2] + wave_part[0][3]);
+        const double e = (wave_part[1][0] + wave_part[1][1]) + (wave_part[1][2] + wave_part[1][3]);
+        *out = w0 * a + (p1 ? w1 * e : 0.0);
+    }
+    __syncthreads();   // wave_part may be reused by the workgroup's next item
+}
+
 // Workgroups of `kernel` that the current device holds at once (cached).
 int resident_workgroups(const void *kernel, int block, size_t shm);
 
