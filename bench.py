@@ -269,8 +269,8 @@ def batched_leg(args):
     plan.close()
     return {"workload": "uneven_64_problems_8copies", "problems": len(specs), "plan_ms": round(plan_ms, 4),
             "per_problem_calls_ms": round(call_ms, 4), "speedup": round(call_ms / plan_ms, 3),
-            "plan_grays": round(rays / (plan_ms * 1e-3) / 1e9, 4), "launches_per_step": {"plan": 9,
-                                                                                        "per_problem": 9 * len(specs)}}
+            "plan_grays": round(rays / (plan_ms * 1e-3) / 1e9, 4), "launches_per_step": {"plan": 8,
+                                                                                        "per_problem": 8 * len(specs)}}
 
 
 def serving_leg(args):
