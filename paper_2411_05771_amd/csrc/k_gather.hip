@@ -241,7 +241,7 @@ static_assert(2 * 16 >= 2 + 22 + 2, "detector window too small for the pixel til
 
 // Default gather shape for up to m listed angles: four angle groups with four
 // pixels per thread once there are enough angles to share, else one of each.
-int gather_groups_auto(int m) { return m >= 256 ? 44 : 1; }
+int gather_groups_auto(int m) { return m >= 64 ? 44 : 1; }
 
 size_t gather_items(int n, int batch)
 {
