@@ -19,7 +19,7 @@ HBM budget, continuous batching vs per-call, p50/p99 latency; "cpu_baseline"
 and "parity" -- the FP64 oracle timed on the host and compared with the
 device on oracle-made inputs.
 
-Prints ONE JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+Prints ONE JSON line.  --gpus N > 1 is refused: the path runs on one GPU.
 """
 from __future__ import annotations
 
@@ -44,7 +44,7 @@ METRIC = "sketched fwd+adj GRays/s and EI-loss fwd+bwd step ms at 1e-5 rel err; 
 # MI355X published peaks used for the roofline fraction.
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3          # published fp32 vector peak (packed issue)
-PEAK_FP32_NONPACKED_TFLOPS = 78.6  # 256 CU x 64 lanes x 2 flop x 2.4 GHz (packed fp32 is disabled in this build)
+PEAK_FP32_NONPACKED_TFLOPS = 78.6  # 256 CU x 64 lanes x 2 flop x 2.4 GHz (the kernels are built with packed fp32 off)
 
 WORKLOADS = {
     "ei256": dict(n=256, n_angles=360, n_det=363, copies=16, m=90, batch=1, lam=1.0),
@@ -148,8 +148,8 @@ def timed_steps(run, steps, probe_stage):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sharded design is in DESIGN.md",
-              file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the multi-GPU sharding of the path "
+              "is a design, not built", file=sys.stderr)
         sys.exit(2)
     import torch
 
