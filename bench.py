@@ -64,7 +64,9 @@ def parse():
     ap.add_argument("--serve-jobs", type=int, default=12)
     ap.add_argument("--serve-rate", type=float, default=1.5, help="Poisson arrival rate, jobs per second")
     ap.add_argument("--budget-gb", type=float, default=4.0, help="HBM budget of the serving leg")
-    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (text)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file (text); default: a scratch copy of the package's MI355X defaults")
+    ap.add_argument("--tune-reps", type=int, default=5, help="timed launches per autotuner candidate")
     return ap.parse_args()
 
 
@@ -151,6 +153,13 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the multi-GPU sharding of the path "
               "is a design, not built", file=sys.stderr)
         sys.exit(2)
+    if args.tune_cache is None:
+        # the package's MI355X tuning of these workloads (autotuner output, 15
+        # timed launches per candidate), copied so that new entries stay local
+        import shutil
+        import tempfile
+        args.tune_cache = os.path.join(tempfile.mkdtemp(prefix="skei_tune_"), "tune.txt")
+        shutil.copyfile(os.path.join(ROOT, "paper_2411_05771_amd", "tuned", "mi355x.txt"), args.tune_cache)
     import torch
 
     from paper_2411_05771_amd import capi, ei, ops, synth
@@ -173,7 +182,7 @@ def main():
 
     # the product path: a one-problem EI plan, autotuned (cached per shape)
     plan = ei.EIPlan([ei.EIProblem(geom, x0, y, sketch, cs, lam)])
-    tuned = plan.autotune(reps=5, cache_path=args.tune_cache)
+    tuned = plan.autotune(reps=args.tune_reps, cache_path=args.tune_cache)
     # the one-call entry point, for reference
     single = ei.EIStep(geom, y, sketch, cs, lam)
     grad = torch.empty_like(x0)
@@ -258,7 +267,7 @@ def batched_leg(args):
         for s_, pr in zip(steps, probs):
             s_(pr.x, pr.grad)
     plan = ei.EIPlan(probs)
-    plan.autotune(reps=3, cache_path=args.tune_cache)
+    plan.autotune(reps=max(3, args.tune_reps // 2), cache_path=args.tune_cache)
     reps = 5
     for _ in range(2):
         plan.run()
