@@ -66,6 +66,10 @@ def test_fused_ei_loss_grad_matches_oracle(skei, orc, shape):
     # deterministic: a second call gives bitwise the same loss and gradient
     loss2, grad2 = step(to_dev(x0))
     assert float(loss2.item()) == got_l and torch.equal(grad2, grad)
+    # the loss alone (formed by its own launch) is bitwise the loss formed
+    # inside the gradient step's launches
+    loss3, _ = step(to_dev(x0), want_grad=False)
+    assert float(loss3.item()) == got_l
 
 
 def test_autograd_matches_fused_step(skei, orc):
