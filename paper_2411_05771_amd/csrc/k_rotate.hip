@@ -60,32 +60,51 @@ __device__ __forceinline__ void rotate_item(const RotJob &J, long long item)
     const int dx = threadIdx.x & 15, dy0 = threadIdx.x >> 4;   // rows dy0, dy0 + 4, dy0 + 8, dy0 + 12
     const float *img = J.x + (size_t)b * n * n;
     const double cN = 0.5 * (double)(n - 1);
-    const float co = J.cs ? J.cs[2 * c] : 1.0f, si = J.cs ? J.cs[2 * c + 1] : 0.0f;
+    // c is uniform over the workgroup and the rotation table is read-only
+    // while kernels run: scalar loads
+    const cword_t *csw = J.cs ? (const cword_t *)(J.cs + 2 * __builtin_amdgcn_readfirstlane(c)) : nullptr;
+    const float co = csw ? __uint_as_float(csw[0]) : 1.0f, si = csw ? __uint_as_float(csw[1]) : 0.0f;
+    // Every tap is loaded unconditionally from a clamped address and zeroed
+    // when it falls outside the image, so the sixteen loads of a thread are
+    // all in flight together; adding an exact zero leaves a sum unchanged.
     float acc[4];
+    if (J.cs) {
+        float v[4][4], w[4][4];
 #pragma unroll
-    for (int r = 0; r < 4; r++) {
-        const int dy = dy0 + 4 * r, i = i0 + dy, j = j0 + dx;
-        float a = 0.0f;
-        if (i < n && j < n) {
-            if (J.cs) {
-                const Sample sp = sample_point(i, j, co, si, cN);
+        for (int r = 0; r < 4; r++) {
+            const Sample sp = sample_point(i0 + dy0 + 4 * r, j0 + dx, co, si, cN);
 #pragma unroll
-                for (int di = 0; di < 2; di++) {
-                    const int ii = sp.i0 + di;
-                    const float wv = di ? sp.av : 1.0f - sp.av;
-#pragma unroll
-                    for (int dj = 0; dj < 2; dj++) {
-                        const int jj = sp.j0 + dj;
-                        const float wu = dj ? sp.au : 1.0f - sp.au;
-                        if (ii >= 0 && ii < n && jj >= 0 && jj < n) a = fmaf(wv * wu, img[(size_t)ii * n + jj], a);
-                    }
-                }
-            } else {
-                a = img[(size_t)i * n + j];
+            for (int k = 0; k < 4; k++) {
+                const int di = k >> 1, dj = k & 1;
+                const int ii = sp.i0 + di, jj = sp.j0 + dj;
+                const bool ok = ii >= 0 && ii < n && jj >= 0 && jj < n;
+                const float t = img[ok ? (size_t)ii * n + jj : 0];
+                v[r][k] = ok ? t : 0.0f;
+                w[r][k] = (di ? sp.av : 1.0f - sp.av) * (dj ? sp.au : 1.0f - sp.au);
             }
-            if (J.out) J.out[(size_t)bc * n * n + (size_t)i * n + j] = a;
         }
-        acc[r] = a;
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            float a = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 4; k++) a = fmaf(w[r][k], v[r][k], a);
+            acc[r] = a;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int i = i0 + dy0 + 4 * r, j = j0 + dx;
+            const bool ok = i < n && j < n;
+            const float t = img[ok ? (size_t)i * n + j : 0];
+            acc[r] = ok ? t : 0.0f;
+        }
+    }
+    if (J.out) {
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int i = i0 + dy0 + 4 * r, j = j0 + dx;
+            if (i < n && j < n) J.out[(size_t)bc * n * n + (size_t)i * n + j] = acc[r];
+        }
     }
     if (J.outT) {
         __syncthreads();   // an earlier item of this workgroup may still read the tile
@@ -117,7 +136,8 @@ __device__ __forceinline__ void rotate_adj_item(const RotAdjJob &J, long long it
     const int n = J.n, copies = J.copies;
     const long long blocks = ((long long)n * n + kRotPix - 1) / kRotPix;
     const long long b = item / blocks;
-    const int px = threadIdx.x & (kRotPix - 1), grp = threadIdx.x / kRotPix;
+    // one wave per copy group: grp is wave-uniform, so a copy's cos / sin are scalar loads
+    const int px = threadIdx.x & (kRotPix - 1), grp = __builtin_amdgcn_readfirstlane(threadIdx.x / kRotPix);
     const int p = (int)(item - b * blocks) * kRotPix + px;
     const bool in = p < n * n;
     float acc = 0.0f;
@@ -126,29 +146,30 @@ __device__ __forceinline__ void rotate_adj_item(const RotAdjJob &J, long long it
         const double cN = 0.5 * (double)(n - 1);
         const double Xp = (double)jp - cN, Yp = (double)ip - cN;
         for (int c = grp; c < copies; c += kRotGroups) {
-            const float co = J.cs[2 * c], si = J.cs[2 * c + 1];
+            // the rotation table is read-only while kernels run: scalar loads
+            const cword_t *csw = (const cword_t *)(J.cs + 2 * c);
+            const float co = __uint_as_float(csw[0]), si = __uint_as_float(csw[1]);
             const float *hc = J.h + ((size_t)b * copies + c) * n * n;
             // centre of the candidate set: the output position whose sample is p'
             const double colc = fma((double)co, Xp, fma(-(double)si, Yp, cN));
             const double rowc = fma((double)si, Xp, fma((double)co, Yp, cN));
             const double hw = fabs((double)co) + fabs((double)si) + 1e-6;
             const int jlo = (int)ceil(colc - hw), ilo = (int)ceil(rowc - hw);
+            // all nine candidates are loaded (clamped address) before any is
+            // used; a candidate that does not touch p' contributes an exact zero
+            float v[9], w[9];
 #pragma unroll
-            for (int di = 0; di < 3; di++) {
-                const int i = ilo + di;
-                if (i < 0 || i >= n) continue;
-#pragma unroll
-                for (int dj = 0; dj < 3; dj++) {
-                    const int j = jlo + dj;
-                    if (j < 0 || j >= n) continue;
-                    const Sample sp = sample_point(i, j, co, si, cN);
-                    const int ei = ip - sp.i0, ej = jp - sp.j0;
-                    if ((unsigned)ei > 1u || (unsigned)ej > 1u) continue;
-                    const float wv = ei ? sp.av : 1.0f - sp.av;
-                    const float wu = ej ? sp.au : 1.0f - sp.au;
-                    acc = fmaf(wv * wu, hc[(size_t)i * n + j], acc);
-                }
+            for (int k = 0; k < 9; k++) {
+                const int i = ilo + k / 3, j = jlo + k % 3;
+                const Sample sp = sample_point(i, j, co, si, cN);
+                const int ei = ip - sp.i0, ej = jp - sp.j0;
+                const bool ok = i >= 0 && i < n && j >= 0 && j < n && (unsigned)ei <= 1u && (unsigned)ej <= 1u;
+                const float t = hc[ok ? (size_t)i * n + j : (size_t)p];
+                v[k] = ok ? t : 0.0f;
+                w[k] = (ei ? sp.av : 1.0f - sp.av) * (ej ? sp.au : 1.0f - sp.au);
             }
+#pragma unroll
+            for (int k = 0; k < 9; k++) acc = fmaf(w[k], v[k], acc);
         }
     }
     __syncthreads();   // an earlier item of this workgroup may still read part[]
