@@ -136,7 +136,11 @@ int skei_fbp_adj(const skei_geom *g, const float *x, int batch, const int32_t *a
 /* Rotations T_phi (Sec. 4.1.3 group of rotations), bilinear, zero fill:
  *   out[b][c](p) = x[b](R(-phi_c) p)   about the image centre, i.e. the
  *   output pixel at (X, Y) samples x at (cos X + sin Y, -sin X + cos Y).
- * cos_sin: device float [copies][2] = (cos phi_c, sin phi_c).
+ * cos_sin: device float [copies][2] = (cos phi_c, sin phi_c), a point of the
+ *   unit circle up to float rounding: the transpose visits the 3 x 3 output
+ *   pixels around each input pixel's preimage, which holds every output that
+ *   can reach it only while |cos| + |sin| <= sqrt(2).  Other pairs give an
+ *   unspecified (but in-bounds) result; they are not checked.
  * skei_rotate:     x [batch][N][N] -> out [batch][copies][N][N].
  * skei_rotate_adj: h [batch][copies][N][N] -> g [batch][N][N],
  *                  g[b] = sum_c T_{phi_c}^T h[b][c]  (exact transpose; gather). */

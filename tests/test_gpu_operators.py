@@ -173,6 +173,25 @@ def test_rotation_parity_and_adjoint(skei, orc):
     assert np.array_equal(zz[0], x) and np.array_equal(zz[1], np.rot90(x, -1))
 
 
+@pytest.mark.parametrize("n,copies,batch", [(37, 5, 2), (17, 3, 1), (2, 1, 2)])
+def test_rotation_ragged_tiles(skei, orc, n, copies, batch):
+    """Images that are not a whole number of tiles (partial tiles, and taps
+    clamped at every border), copy counts that leave some copy groups empty,
+    and batches of two."""
+    rng = np.random.default_rng(100 + n)
+    x = f32(rng.uniform(0, 1, (batch, n, n)))
+    cs = f32(synth.cos_sin(rng.uniform(0, 2 * np.pi, copies)))
+    csd = to_dev(cs)
+    z = skei.rotate_(to_dev(x), csd)
+    e = relerr(host(z), orc.rotate(x, cs))
+    h = f32(rng.uniform(0, 1, (batch, copies, n, n)))
+    g = skei.rotate_adj_(to_dev(h), csd)
+    e_adj = relerr(host(g), orc.rotate_adj(h, cs))
+    gap = adjoint_gap(host(z), h, x, host(g))
+    print(f"[rotate n={n} C={copies} B={batch}] {e:.3e} adj {e_adj:.3e} gap {gap:.2e}")
+    assert e < TOL and e_adj < TOL and gap < ADJ_TOL
+
+
 def test_sumsq(skei):
     a = np.random.default_rng(4).standard_normal(1_000_003)
     b = np.random.default_rng(5).standard_normal(1_000_003)
