@@ -96,22 +96,31 @@ __device__ __forceinline__ void ramp_item(const RampJob &J, long long r, double 
             L[i] = at(i - 2 * e0 - 1);   // p[k0 + i - d], d = 2 e0 + 1
             R[i] = at(i + 2 * e0 + 1);   // p[k0 + i + d]
         }
-        for (int e = e0; e < e0 + ES; e += 4) {
+        // The taps are a multiple of 16, so pad = 2 E + 10 = 2 (mod 8) and e0
+        // is a multiple of 4.  A 4-tap step at e then reads left elements
+        // a - 2u and a - 2u - 1 with a = pad - 2e - 2 = 0 (mod 8), and right
+        // elements b + 2u and b + 2u + 1 with b = pad + 2e + 9 = 3 (mod 8):
+        // their skewed positions are fixed offsets from 9 a / 8 and 9 (b - 3) / 8,
+        // and both bases move by 9 per step, so no read needs address arithmetic.
+        constexpr int kL[4][2] = {{0, -2}, {-3, -4}, {-5, -6}, {-7, -8}};   // L[1], L[0]
+        constexpr int kR[4][2] = {{3, 4}, {5, 6}, {7, 9}, {10, 11}};       // R[V - 2], R[V - 1]
+        const double *pl = c + 9 * ((pad - 2 * e0 - 2) >> 3);
+        const double *pr = c + 9 * ((pad + 2 * e0 + 9) >> 3);
+        for (int e = e0; e < e0 + ES; e += 4, pl -= 9, pr += 9) {
 #pragma unroll
             for (int u = 0; u < 4; u++) {
                 const double h = hodd[e + u];
 #pragma unroll
                 for (int i = 0; i < V; i++) acc[i] = fma(h, L[i] + R[i], acc[i]);
                 // d -> d + 2: the left window moves two entries down, the right one two up
-                const int d = 2 * (e + u) + 1;
 #pragma unroll
                 for (int i = V - 1; i >= 2; i--) L[i] = L[i - 2];
-                L[1] = at(-d - 1);
-                L[0] = at(-d - 2);
+                L[1] = pl[kL[u][0]];   // p[k0 - d - 1]
+                L[0] = pl[kL[u][1]];   // p[k0 - d - 2]
 #pragma unroll
                 for (int i = 0; i < V - 2; i++) R[i] = R[i + 2];
-                R[V - 2] = at(d + V);
-                R[V - 1] = at(d + V + 1);
+                R[V - 2] = pr[kR[u][0]];   // p[k0 + d + V]
+                R[V - 1] = pr[kR[u][1]];   // p[k0 + d + V + 1]
             }
         }
         if (sg > 0) {
