@@ -66,7 +66,9 @@ __device__ __forceinline__ void gather_item(const GatherJob &J, long long item)
     const int b = (int)(item / tiles), tile = (int)(item - (long long)b * tiles);
     const int i0 = (tile / tiles_x) * TILE, j0 = (tile % tiles_x) * TILE;
     const int tid = threadIdx.x;
-    const int pg = tid % TPG, ga = tid / TPG;
+    // TPG is a multiple of 64, so the angle group is wave-uniform: scalar loop control
+    static_assert(TPG % 64 == 0, "angle groups are whole waves");
+    const int pg = tid % TPG, ga = __builtin_amdgcn_readfirstlane(tid / TPG);
     // pixel v of this thread: row pg / CW, column pg % CW + v CW
     auto pix = [&](int v) { return (pg / CW) * TILE + pg % CW + v * CW; };
     const double fdy = (double)(pg / CW);
@@ -108,6 +110,7 @@ __device__ __forceinline__ void gather_item(const GatherJob &J, long long item)
                 win[e] = make_float2(v0, v1 - v0);
         }
         __syncthreads();
+#pragma unroll 2
         for (int a4 = 0; a4 < Ac; a4 += kClasses) {
 #pragma unroll
             for (int c = 0; c < NC; c++) {
