@@ -245,8 +245,12 @@ int skei_ei_plan_get_config(const skei_ei_plan *plan, int stage, int *dispatch, 
  * plan's own problems (hipEvents, median of `reps` launches on `stream`) and
  * keeps the fastest.  Choices are cached per stage under a signature of the
  * stage's work list (sizes, not pointers) -- in memory, and in the text file
- * `cache_path` when it is not NULL (read first, appended to).  The plan must
- * have been run once (its buffers hold finite values).  Synchronises. */
+ * `cache_path` when it is not NULL (read first, appended to).  It first runs
+ * the whole step once so that every candidate is timed on real intermediate
+ * values.  Problems' images are never changed: the fused gradient step
+ * (skei_ei_problem.step) is left out of every run the tuner makes, and the
+ * losses and gradients it leaves behind are those of the unchanged images.
+ * Synchronises. */
 int skei_ei_plan_autotune(skei_ei_plan *plan, void *stream, int reps, const char *cache_path);
 
 /* Profiling probe for skei_ei_loss_grad and skei_ei_plan_run: when set, the

@@ -100,6 +100,7 @@ struct skei_ei_plan {
     size_t dev_bytes = 0;
     WorkQueue *queues = nullptr;   // two sets per stage, at the start of dev
     int parity[kStages] = {};      // the set the next launch of a stage uses
+    bool tuning = false;           // while true the fused x -= step * grad is left out
 };
 
 namespace {
@@ -162,6 +163,10 @@ int plan_build(skei_ei_plan *P)
             adj.push_back(J.adj[0]);
             adj.push_back(J.adj[1]);
             max_m_adj = std::max(max_m_adj, std::max(p.m, p.m_mc));
+            if (P->tuning) {   // timing runs must not move the caller's image
+                J.radj.x_upd = nullptr;
+                J.radj.step = 0.0f;
+            }
             radj.push_back(J.radj);
         }
     }
@@ -468,7 +473,15 @@ int skei_ei_plan_autotune(skei_ei_plan *plan, void *stream, int reps, const char
         hipEventDestroy(e0);
         return SKEI_ELAUNCH;
     }
-    int rc = SKEI_OK;
+    // Every candidate is timed on real intermediate values: one whole run
+    // first fills the plan's buffers.  The fused gradient step is left out of
+    // that run and of every timed launch, so x is unchanged by tuning.
+    plan->tuning = true;
+    int rc = plan_build(plan);
+    for (int s = 0; s < kStages && rc == SKEI_OK; s++) {
+        if (s > SKEI_STAGE_REDUCE && !plan->any_grad) break;
+        rc = run_stage(plan, s, st);
+    }
     for (int s = 0; s < kStages && rc == SKEI_OK; s++) {
         if (plan->tab[s].total <= 0) continue;
         const std::string key = stage_signature(plan, s);
@@ -513,7 +526,9 @@ int skei_ei_plan_autotune(skei_ei_plan *plan, void *stream, int reps, const char
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
-    return rc;
+    plan->tuning = false;
+    const int rb = plan_build(plan);   // the chosen shapes, with the gradient step restored
+    return rc ? rc : rb;
 }
 
 }  // extern "C"

@@ -193,8 +193,8 @@ class EIPlan:
         return d.value, sh.value
 
     def autotune(self, reps: int = 5, cache_path: str | None = None):
-        """Times every stage's (dispatch, shape) candidates and keeps the best."""
-        self.run()
+        """Times every stage's (dispatch, shape) candidates and keeps the best.
+        The problems' images are left unchanged (no gradient step is applied)."""
         capi.call("skei_ei_plan_autotune", self.handle, ops._stream(), int(reps),
                   cache_path.encode() if cache_path else None)
         return {name: self.config(name) for name in capi.STAGES}

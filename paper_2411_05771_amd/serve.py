@@ -25,6 +25,7 @@ logic is tested on the CPU with fakes.
 from __future__ import annotations
 
 import ctypes
+import itertools
 import math
 import time
 from collections import deque
@@ -187,6 +188,7 @@ class GpuExecutor:
         self.geoms = {}
         self.host_y = {}
         self._plans = {}
+        self._tokens = itertools.count()
         self.plan_builds = 0
 
     # ---------------------------------------------------------------- inputs
@@ -231,6 +233,7 @@ class GpuExecutor:
         na, ratio, m = spec["n_angles"], spec["ratio"], spec["m"]
         subsets = np.stack([k + ratio * np.arange(m) for k in range(ratio)]).astype(np.int32)
         st = _JobState()
+        st.token = next(self._tokens)   # stable identity for the plan cache (never reused)
         st.spec = spec
         st.cost = iteration_cost(spec)
         st.sk_table = torch.from_numpy(subsets).to(self.dev)
@@ -251,8 +254,11 @@ class GpuExecutor:
         st.cs.copy_(st.cs_table[st.it])
 
     def _plan(self, members):
+        """The plan of a class of jobs, cached under the members' tokens (a
+        token is drawn once per job and never reused, so a cached plan is
+        only ever bound to the problems of exactly these jobs)."""
         from . import ei
-        key = tuple(id(st) for st in members)
+        key = tuple(st.token for st in members)
         plan = self._plans.get(key)
         if plan is None:
             plan = ei.EIPlan([st.problem for st in members])
@@ -289,8 +295,8 @@ class GpuExecutor:
             for r in sorted(classes, reverse=True):
                 used.add(self._run(classes[r], r))
         else:
-            for st in states:
-                used.add(self._run([st], 1))
+            for st, r in zip(states, reps):
+                used.add(self._run([st], r))
         # plans of classes that no longer exist free their tables
         for key in [k for k in self._plans if k not in used]:
             self._plans.pop(key).close()

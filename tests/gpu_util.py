@@ -32,14 +32,3 @@ def adjoint_gap(ax, y, x, aty):
 def f32(a):
     """Round to float32 and back: the exact values both sides receive."""
     return np.asarray(a, dtype=np.float32).astype(np.float64)
-
-
-def ei_kappa(orc, x, y, na, cs, lam, grad):
-    """Cancellation factor of an EI gradient: the size of its largest term
-    (2 A^T A x, 2 A^T y, 2 lambda T x) over the size of the gradient."""
-    n = x.shape[-1]
-    g_mc = 2 * orc.radon_adj(orc.radon_fwd(x, na, y.shape[-1]), n, na)
-    g_mc2 = 2 * orc.radon_adj(y, n, na)
-    z = orc.rotate(x, cs)
-    terms = max(np.max(np.abs(g_mc)), np.max(np.abs(g_mc2)), 2 * lam * np.max(np.abs(z)))
-    return terms / np.max(np.abs(grad))

@@ -7,12 +7,8 @@ sigma = 0.01 max(A x_true), the image under evaluation x = FBP(y) (the
 test-time starting point F(A^dagger y) with F = identity), 16 rotations
 phi ~ U[0, 2 pi), a seeded random quarter sketch.
 
-Tolerance.  Loss and gradient are differences of nearly equal terms (for
-instance r_MC = y - A x is ~1-5 % of y), so float32 error in the operators
-(<= 1e-5 of their own max-norm, the operator bar) is amplified by the ratio
-kappa = ||terms||_inf / ||result||_inf.  The bar applied is
-relerr <= 1e-5 * max(1, kappa), with kappa measured by the oracle for the
-very inputs of the test."""
+Bar: relative error <= 1e-5 in the loss and relative max-norm error <= 1e-5
+in the gradient."""
 import numpy as np
 import pytest
 import torch
@@ -34,16 +30,6 @@ def workload(orc, n, na, nd, batch, copies, m, seed_shift=0):
     return x0, y, idx, cs
 
 
-def kappa(orc, x, y, na, idx, cs, lam, grad):
-    """Cancellation factor of the gradient: size of its largest term over its size."""
-    n = x.shape[-1]
-    g_mc = 2 * orc.radon_adj(orc.radon_fwd(x, na, y.shape[-1]), n, na)
-    g_mc2 = 2 * orc.radon_adj(y, n, na)
-    z = orc.rotate(x, cs)
-    terms = max(np.max(np.abs(g_mc)), np.max(np.abs(g_mc2)), 2 * lam * np.max(np.abs(z)))
-    return terms / np.max(np.abs(grad))
-
-
 @pytest.mark.parametrize("shape", [(64, 60, 91, 1, 4, 15), (256, 360, 363, 1, 16, 90)],
                          ids=["plain64", "ei256"])
 def test_fused_ei_loss_grad_matches_oracle(skei, orc, shape):
@@ -59,8 +45,7 @@ def test_fused_ei_loss_grad_matches_oracle(skei, orc, shape):
     got_l = float(loss.item())
     e_l = abs(got_l - want_l) / abs(want_l)
     e_g = relerr(host(grad), want_g)
-    k = kappa(orc, x0, y, na, idx, cs, lam, want_g)
-    print(f"loss {got_l:.9e} vs {want_l:.9e} rel {e_l:.2e}; grad relerr {e_g:.2e}; kappa {k:.1f}")
+    print(f"[ei] loss {got_l:.9e} vs {want_l:.9e} rel {e_l:.2e}; grad relerr {e_g:.2e}", flush=True)
     assert e_l < 1e-5
     assert e_g < 1e-5
     # deterministic: a second call gives bitwise the same loss and gradient

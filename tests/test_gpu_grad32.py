@@ -10,15 +10,15 @@ central difference equals the directional derivative up to FP64 rounding;
 the difference is taken on the oracle only (in FP32 a step of 1e-4 would be
 dominated by cancellation).
 
-Bar: elementwise relerr <= 1e-5 * max(1, kappa) as in the single-image EI
-test (kappa = the gradient's cancellation factor, measured by the oracle);
-directional: |<g - g_oracle, v>| <= 1e-5 * kappa * ||g_oracle||_2 ||v||_2.
+Bar: elementwise relative max-norm error <= 1e-5 over the whole batch and
+for every image on its own; directional: |<g - g_oracle, v>| <= 1e-5 *
+||g_oracle||_2 ||v||_2 for every direction v.
 """
 import numpy as np
 import pytest
 import torch
 
-from gpu_util import ei_kappa, f32, host, relerr, to_dev
+from gpu_util import f32, host, relerr, to_dev
 from paper_2411_05771_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -51,9 +51,8 @@ def test_batch32_gradient_against_oracle(skei, orc):
     print(f"\n[grad32] B={B} N={N} angles={NA} det={ND} copies={C} m={M}", flush=True)
     x0, y, idx, cs = inputs(orc)
     want_l, want_g = orc.ei_loss_grad(x0, y, NA, idx, cs, 1.0)
-    kap = max(ei_kappa(orc, x0[i:i + 1], y[i:i + 1], NA, cs, 1.0, want_g[i:i + 1]) for i in (0, B // 2, B - 1))
-    bar = 1e-5 * max(1.0, kap)
-    print(f"[grad32] oracle loss {want_l:.6e}, kappa ~ {kap:.1f}", flush=True)
+    bar = 1e-5
+    print(f"[grad32] oracle loss {want_l:.6e}", flush=True)
 
     geom = skei.Geometry(N, NA, ND)
     sk = geom.sketch(idx)
@@ -69,9 +68,13 @@ def test_batch32_gradient_against_oracle(skei, orc):
     e_f, e_a = relerr(g_fused, want_g), relerr(g_auto, want_g)
     print(f"[grad32] loss relerr {e_l:.2e}; grad relerr fused {e_f:.2e} autograd {e_a:.2e} (bar {bar:.1e})",
           flush=True)
+    per_image = [max(relerr(g[i], want_g[i]) for g in (g_fused, g_auto)) for i in range(B)]
+    print(f"[grad32] worst per-image grad relerr {max(per_image):.2e} (image {int(np.argmax(per_image))})",
+          flush=True)
     assert e_l <= 1e-5
     assert abs(float(l_auto.item()) - want_l) / abs(want_l) <= 1e-5
     assert e_f <= bar and e_a <= bar
+    assert max(per_image) <= bar
 
     vs = directions()
     gn = np.linalg.norm(want_g)

@@ -5,8 +5,8 @@ Each problem of a plan must give bitwise the loss and gradient of the
 one-problem fused step (skei_ei_loss_grad) on the same inputs, whatever the
 dispatch mode (persistent queues or one workgroup per item), the launch
 shapes (rays per thread, angle groups per pixel) or the autotuner's choice;
-and it must match the FP64 oracle within the EI tolerance (relerr <= 1e-5 *
-max(1, kappa), kappa the gradient's cancellation factor).
+and it must match the FP64 oracle to a relative max-norm error of 1e-5 in
+both the loss and the gradient.
 
 Inputs: seeded ellipse phantoms, y = A x_true + 1 % noise, x = FBP(y), a
 seeded random sketch of N_theta / ratio angles and seeded rotations per
@@ -17,7 +17,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import ei_kappa, f32, host, relerr, to_dev
+from gpu_util import f32, host, relerr, to_dev
 from paper_2411_05771_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -122,15 +122,15 @@ def test_plan_matches_oracle(skei, orc):
         pr, (x0, y, idx, cs) = oracle_problem(skei, ei, orc, p)
         probs.append(pr)
         wl, wg = orc.ei_loss_grad(x0, y, p["n_angles"], idx, cs, 1.0)
-        want.append((wl, wg, ei_kappa(orc, x0, y, p["n_angles"], cs, 1.0, wg)))
+        want.append((wl, wg))
     plan = ei.EIPlan(probs)
     losses, grads = plan.run()
-    for i, (wl, wg, kap) in enumerate(want):
+    for i, (wl, wg) in enumerate(want):
         e_l = abs(float(losses[i].item()) - wl) / abs(wl)
         e_g = relerr(host(grads[i]), wg)
-        print(f"[plan-oracle] problem {i}: loss relerr {e_l:.2e}  grad relerr {e_g:.2e}  kappa {kap:.1f}", flush=True)
+        print(f"[plan-oracle] problem {i}: loss relerr {e_l:.2e}  grad relerr {e_g:.2e}", flush=True)
         assert e_l <= 1e-5
-        assert e_g <= 1e-5 * max(1.0, kap)
+        assert e_g <= 1e-5
     plan.close()
 
 
@@ -138,9 +138,12 @@ def test_plan_uneven_64_problems(skei, orc):
     """The full uneven workload: 64 problems, 8 copies each, one launch per stage."""
     from paper_2411_05771_amd import ei
     specs = synth.uneven_problems()
-    # the two cheapest problems are also checked against the oracle, so their
-    # inputs are made by the oracle; the others are made on the device
-    sampled = sorted(range(len(specs)), key=lambda i: specs[i]["n"] ** 2 * specs[i]["n_angles"])[:2]
+    # the two cheapest problems and the cheapest 512 x 512 one (726 detectors)
+    # are also checked against the oracle, so their inputs are made by the
+    # oracle; the others are made on the device
+    cost = lambda i: specs[i]["n"] ** 2 * specs[i]["n_angles"]
+    sampled = sorted(range(len(specs)), key=cost)[:2]
+    sampled.append(min((i for i in range(len(specs)) if specs[i]["n"] == 512), key=cost))
     probs, oracle_inputs = [], {}
     for i, p in enumerate(specs):
         if i in sampled:
@@ -158,13 +161,12 @@ def test_plan_uneven_64_problems(skei, orc):
         p, pr = specs[i], probs[i]
         x0, y, idx, cs = oracle_inputs[i]
         wl, wg = orc.ei_loss_grad(x0, y, p["n_angles"], idx, cs, 1.0)
-        kap = ei_kappa(orc, x0, y, p["n_angles"], cs, 1.0, wg)
         e_l = abs(float(plan.losses[i].item()) - wl) / abs(wl)
         e_g = relerr(host(pr.grad), wg)
-        print(f"[plan-64] problem {i} n={p['n']} n_angles={p['n_angles']} m={p['m']}: loss {e_l:.2e} "
-              f"grad {e_g:.2e} kappa {kap:.1f}", flush=True)
+        print(f"[plan-64] problem {i} n={p['n']} n_angles={p['n_angles']} n_det={p['n_det']} m={p['m']}: "
+              f"loss {e_l:.2e} grad {e_g:.2e}", flush=True)
         assert e_l <= 1e-5
-        assert e_g <= 1e-5 * max(1.0, kap)
+        assert e_g <= 1e-5
     plan.close()
 
 
@@ -191,12 +193,11 @@ def test_plan_degenerate_problems(skei, orc):
         assert_bitwise(plan, refs, f"degenerate, dispatch {d}")
     for p, pr, (x0, y, idx, cs), (rl, rg) in zip(specs, probs, inputs, refs):
         wl, wg = orc.ei_loss_grad(x0, y, p["n_angles"], idx, cs, 1.0)
-        kap = ei_kappa(orc, x0, y, p["n_angles"], cs, 1.0, wg)
         e_l = abs(float(rl.item()) - wl) / abs(wl)
         e_g = relerr(host(rg), wg)
-        print(f"[plan-degenerate] n={p['n']} m={p['m']} C={p['copies']}: loss {e_l:.2e} grad {e_g:.2e} "
-              f"kappa {kap:.1f}", flush=True)
-        assert e_l <= 1e-5 and e_g <= 1e-5 * max(1.0, kap)
+        print(f"[plan-degenerate] n={p['n']} m={p['m']} C={p['copies']}: loss {e_l:.2e} grad {e_g:.2e}",
+              flush=True)
+        assert e_l <= 1e-5 and e_g <= 1e-5
     plan.close()
 
 
@@ -215,9 +216,33 @@ def test_autotuned_ei_workload_plan_matches_oracle(skei, orc):
     print(f"\n[plan-ei256] tuned {tuned}", flush=True)
     assert_bitwise(plan, [ref], "autotuned EI workload")
     wl, wg = orc.ei_loss_grad(x0, y, p["n_angles"], idx, cs, 1.0)
-    kap = ei_kappa(orc, x0, y, p["n_angles"], cs, 1.0, wg)
     e_l = abs(float(plan.losses[0].item()) - wl) / abs(wl)
     e_g = relerr(host(pr.grad), wg)
-    print(f"[plan-ei256] loss {e_l:.2e} grad {e_g:.2e} kappa {kap:.1f}", flush=True)
-    assert e_l <= 1e-5 and e_g <= 1e-5 * max(1.0, kap)
+    print(f"[plan-ei256] loss {e_l:.2e} grad {e_g:.2e}", flush=True)
+    assert e_l <= 1e-5 and e_g <= 1e-5
+    plan.close()
+
+
+def test_autotune_leaves_the_image_alone(skei):
+    """A plan whose problem takes a fused gradient step (step != 0): tuning
+    times many launches of every stage but must not move x; the next run then
+    takes exactly one step, x - step * grad."""
+    from paper_2411_05771_amd import ei
+    p = synth.uneven_problems(count=1, sizes=(48,), angles=(40, 60), ratios=(2,), copies=3, seed=6300)[0]
+    base = gpu_problem(skei, ei, p)
+    x_before = base.x.clone()
+    pr = ei.EIProblem(base.geom, base.x, base.y, base.sk, base.cs, 1.0, step=1e-3)
+    plan = ei.EIPlan([pr])
+    plan.autotune(reps=3)
+    torch.cuda.synchronize()
+    assert torch.equal(pr.x, x_before), "autotuning moved the image"
+    ref = single_call(ei, pr)            # gradient at the unchanged image
+    plan.run()
+    torch.cuda.synchronize()
+    assert torch.equal(pr.grad, ref[1])
+    want = torch.addcmul(x_before, ref[1], torch.full_like(x_before, -1e-3))
+    print(f"\n[plan-autotune] step applied, max |x - (x0 - step g)| = {float((pr.x - want).abs().max()):.2e}",
+          flush=True)
+    assert float((pr.x - want).abs().max()) <= 1e-6 * float(x_before.abs().max())
+    assert not torch.equal(pr.x, x_before)
     plan.close()

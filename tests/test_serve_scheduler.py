@@ -169,3 +169,79 @@ def test_executor_may_advance_jobs_by_several_iterations():
     steps_of = {j.spec["job"]: sum(j.spec["job"] in ids for _, ids in ex.steps) for j in rep.done}
     assert steps_of == {0: 2, 1: 4}
     assert rep.done[0].spec["job"] == 0 and rep.done[0].finished < rep.done[1].finished
+
+
+# ------------------------------------------------------------------ GpuExecutor plan cache
+class _FakePlan:
+    """Stands in for ei.EIPlan: records which problems every run computes."""
+
+    def __init__(self, problems):
+        self.problems = list(problems)
+        self.runs = []
+        self.closed = False
+
+    def run(self):
+        self.runs.append(list(self.problems))
+
+    def close(self):
+        self.closed = True
+
+
+def _host_executor(monkeypatch, batched=True, fair=False):
+    """A GpuExecutor whose device parts (torch sync, plans, per-iteration
+    input copies) are replaced by host fakes; step() and the plan cache are
+    the real ones."""
+    import itertools
+    import types
+
+    from paper_2411_05771_amd import ei
+    monkeypatch.setattr(ei, "EIPlan", _FakePlan)
+    ex = object.__new__(serve.GpuExecutor)
+    ex.batched, ex.fair, ex.record_loss = batched, fair, False
+    ex._plans, ex._tokens, ex.plan_builds = {}, itertools.count(), 0
+    ex.torch = types.SimpleNamespace(cuda=types.SimpleNamespace(synchronize=lambda: None))
+    ex._inputs = lambda st: None
+    return ex
+
+
+def _state(ex, iters=1, cost=1.0):
+    st = serve._JobState()
+    st.token = next(ex._tokens)          # as GpuExecutor.start draws it
+    st.problem = object()
+    st.spec = {"iters": iters}
+    st.it = 0
+    st.cost = cost
+    return st
+
+
+def test_plan_cache_never_serves_a_finished_jobs_plan(monkeypatch):
+    """A job finishes and a new one-member class is admitted at the next step.
+    CPython may give the new job's state the finished state's address; the
+    cached plan must still never be the finished job's (it would compute the
+    finished job's problem and leave the new job's image untouched)."""
+    ex = _host_executor(monkeypatch)
+    first = _state(ex)
+    ex.step([first])
+    old_id = id(first)
+    del first                             # the server drops a finished job's state
+    keep, new = [], None
+    for _ in range(1000):                 # try to land a new state on the freed address
+        st = _state(ex)
+        if id(st) == old_id:
+            new = st
+            break
+        keep.append(st)
+    new = new if new is not None else _state(ex)
+    ex.step([new])
+    runs = [r for plan in ex._plans.values() for r in plan.runs]
+    assert runs and runs[-1] == [new.problem], "the new job ran another job's plan"
+
+
+def test_per_call_executor_honours_fair_repetitions(monkeypatch):
+    """batched=False with fair=True: each job runs as many iterations as the
+    step reports for it."""
+    ex = _host_executor(monkeypatch, batched=False, fair=True)
+    cheap, dear = _state(ex, iters=10, cost=1.0), _state(ex, iters=10, cost=4.0)
+    reps = ex.step([cheap, dear])
+    assert reps == [4, 1]
+    assert cheap.it == 4 and dear.it == 1
