@@ -100,6 +100,18 @@ int skei_geom_set_tuning(skei_geom *g, int op, int group, int lines, int split);
 int skei_radon_fwd(const skei_geom *g, const float *x, int batch,
                    const int32_t *angle_idx, int m, float *y, void *stream);
 
+/* r = S y - A_S x   (the measurement-consistency residual of the EI loss,
+ * Eq. (skeilossttt) / Algorithm 2, with S the listed angles).
+ * x [batch][N][N], y_full [batch][N_theta][N_det] (the whole measured
+ * sinogram) -> r [batch][m][N_det] with r[b][i][k] = y_full[b][angle_idx[i]][k]
+ * minus row i of skei_radon_fwd(x).  The projection is accumulated and the
+ * difference taken in double precision before r is rounded to float32: the
+ * residual is far smaller than y, so rounding A_S x to float first would
+ * cost most of its significant digits.  Same launch shapes and errors as
+ * skei_radon_fwd; y_full must not overlap r. */
+int skei_radon_resid(const skei_geom *g, const float *x, const float *y_full, int batch,
+                     const int32_t *angle_idx, int m, float *r, void *stream);
+
 /* x = A_S^T y   (exact transpose of skei_radon_fwd, computed per pixel as a
  * gather over the m listed angles: no atomics).
  * y [batch][m][N_det] -> x [batch][N][N]. */

@@ -197,6 +197,52 @@ int ei_problem_jobs(const skei_ei_problem &p, const EiBuffers &b, const RayChoic
     return SKEI_OK;
 }
 
+int ei_loss_grad_impl(const skei_geom *g, const float *x, const float *y, int batch, const int32_t *mc_idx,
+                      int m_mc, const int32_t *angle_idx, int m, int copies, const float *cos_sin, float lambda,
+                      double *loss, float *grad, void *work, size_t work_bytes, void *stream)
+{
+    if (!g || !x || !y || !mc_idx || !angle_idx || !cos_sin || !loss || !work) return SKEI_EINVAL;
+    if (batch <= 0 || m_mc <= 0 || m <= 0 || copies <= 0) return SKEI_EINVAL;
+    if ((size_t)batch * copies > 65535) return SKEI_ERANGE;
+    EiBuffers b;
+    if (!ei_carve(g, batch, m_mc, m, copies, work, work_bytes, b)) return SKEI_ESPACE;
+    const skei_ei_problem p{g,      batch, const_cast<float *>(x), y,    mc_idx, m_mc, angle_idx, m, copies, cos_sin,
+                            lambda, loss,  grad,                   0.0f, nullptr, 0};
+    EiJobs J;
+    int rc = ei_problem_jobs(p, b, RayChoice{}, RayChoice{}, J);
+    if (rc) return rc;
+
+    const hipStream_t st = S(stream);
+    const RayShape fwd_sh = merge_shapes(J.fwd_shape[0], J.fwd_shape[1]);
+    if ((rc = staged(SKEI_STAGE_ROTATE, st, [&] { return rotate_run(inline_jobs(J.rot, 2), st); }))) return rc;
+    if ((rc = staged(SKEI_STAGE_FWD, st, [&] { return ray_run(kRayFwd, false, fwd_sh, inline_jobs(J.fwd, 2), st); })))
+        return rc;
+    if ((rc = staged(SKEI_STAGE_RAMP, st,
+                     [&] { return ramp_run(false, ramp_block(g->n_det), ramp_shm(g->n_det), inline_jobs(J.ramp, 2), st); })))
+        return rc;
+    if ((rc = staged(SKEI_STAGE_BP_RESID, st,
+                     [&] { return gather_run(kGatherBackproject, gather_groups_auto(m), inline_jobs(&J.bp, 1), st); })))
+        return rc;
+    // with a gradient, the loss is formed by one item of the RAMP_T launch
+    // (same fixed order) and REDUCE launches nothing
+    if ((rc = staged(SKEI_STAGE_REDUCE, st,
+                     [&] { return grad ? SKEI_OK : reduce_run(inline_jobs(&J.red, 1), st); })))
+        return rc;
+    if (!grad) return SKEI_OK;
+    const RampJob rampT[2] = {make_loss_job(J.red), J.rampT};   // the loss item starts first
+    if ((rc = staged(SKEI_STAGE_BP_T, st,
+                     [&] { return ray_run(kRayBpT, true, J.bpt_shape, inline_jobs(&J.bpt, 1), st); })))
+        return rc;
+    if ((rc = staged(SKEI_STAGE_RAMP_T, st,
+                     [&] { return ramp_run(true, ramp_block(g->n_det), ramp_shm(g->n_det), inline_jobs(rampT, 2), st); })))
+        return rc;
+    if ((rc = staged(SKEI_STAGE_ADJ, st, [&] {
+             return gather_run(kGatherJosephAdj, gather_groups_auto(std::max(m, m_mc)), inline_jobs(J.adj, 2), st);
+         })))
+        return rc;
+    return staged(SKEI_STAGE_ROTATE_ADJ, st, [&] { return rotate_adj_run(inline_jobs(&J.radj, 1), st); });
+}
+
 }  // namespace skei
 
 extern "C" {
@@ -216,6 +262,15 @@ int skei_radon_fwd(const skei_geom *g, const float *x, int batch, const int32_t 
     int rc = check_geom_op(g, x, batch, angle_idx, m, y);
     if (rc) return rc;
     return launch_radon_fwd(g, x, nullptr, batch, angle_idx, m, y, nullptr, g->tune_fwd, S(stream));
+}
+
+int skei_radon_resid(const skei_geom *g, const float *x, const float *y_full, int batch, const int32_t *angle_idx,
+                     int m, float *r, void *stream)
+{
+    int rc = check_geom_op(g, x, batch, angle_idx, m, r);
+    if (rc) return rc;
+    if (!y_full) return SKEI_EINVAL;
+    return launch_radon_fwd(g, x, nullptr, batch, angle_idx, m, r, y_full, g->tune_fwd, S(stream));
 }
 
 int skei_radon_adj(const skei_geom *g, const float *y, int batch, const int32_t *angle_idx, int m, float *x,
@@ -326,46 +381,8 @@ int skei_ei_loss_grad(const skei_geom *g, const float *x, const float *y, int ba
                       int m_mc, const int32_t *angle_idx, int m, int copies, const float *cos_sin, float lambda,
                       double *loss, float *grad, void *work, size_t work_bytes, void *stream)
 {
-    if (!g || !x || !y || !mc_idx || !angle_idx || !cos_sin || !loss || !work) return SKEI_EINVAL;
-    if (batch <= 0 || m_mc <= 0 || m <= 0 || copies <= 0) return SKEI_EINVAL;
-    if ((size_t)batch * copies > 65535) return SKEI_ERANGE;
-    EiBuffers b;
-    if (!ei_carve(g, batch, m_mc, m, copies, work, work_bytes, b)) return SKEI_ESPACE;
-    const skei_ei_problem p{g,      batch, const_cast<float *>(x), y,    mc_idx, m_mc, angle_idx, m, copies, cos_sin,
-                            lambda, loss,  grad,                   0.0f, nullptr, 0};
-    EiJobs J;
-    int rc = ei_problem_jobs(p, b, RayChoice{}, RayChoice{}, J);
-    if (rc) return rc;
-
-    const hipStream_t st = S(stream);
-    const RayShape fwd_sh = merge_shapes(J.fwd_shape[0], J.fwd_shape[1]);
-    if ((rc = staged(SKEI_STAGE_ROTATE, st, [&] { return rotate_run(inline_jobs(J.rot, 2), st); }))) return rc;
-    if ((rc = staged(SKEI_STAGE_FWD, st, [&] { return ray_run(kRayFwd, false, fwd_sh, inline_jobs(J.fwd, 2), st); })))
-        return rc;
-    if ((rc = staged(SKEI_STAGE_RAMP, st,
-                     [&] { return ramp_run(false, ramp_block(g->n_det), ramp_shm(g->n_det), inline_jobs(J.ramp, 2), st); })))
-        return rc;
-    if ((rc = staged(SKEI_STAGE_BP_RESID, st,
-                     [&] { return gather_run(kGatherBackproject, gather_groups_auto(m), inline_jobs(&J.bp, 1), st); })))
-        return rc;
-    // with a gradient, the loss is formed by one item of the RAMP_T launch
-    // (same fixed order) and REDUCE launches nothing
-    if ((rc = staged(SKEI_STAGE_REDUCE, st,
-                     [&] { return grad ? SKEI_OK : reduce_run(inline_jobs(&J.red, 1), st); })))
-        return rc;
-    if (!grad) return SKEI_OK;
-    const RampJob rampT[2] = {make_loss_job(J.red), J.rampT};   // the loss item starts first
-    if ((rc = staged(SKEI_STAGE_BP_T, st,
-                     [&] { return ray_run(kRayBpT, true, J.bpt_shape, inline_jobs(&J.bpt, 1), st); })))
-        return rc;
-    if ((rc = staged(SKEI_STAGE_RAMP_T, st,
-                     [&] { return ramp_run(true, ramp_block(g->n_det), ramp_shm(g->n_det), inline_jobs(rampT, 2), st); })))
-        return rc;
-    if ((rc = staged(SKEI_STAGE_ADJ, st, [&] {
-             return gather_run(kGatherJosephAdj, gather_groups_auto(std::max(m, m_mc)), inline_jobs(J.adj, 2), st);
-         })))
-        return rc;
-    return staged(SKEI_STAGE_ROTATE_ADJ, st, [&] { return rotate_adj_run(inline_jobs(&J.radj, 1), st); });
+    return ei_loss_grad_impl(g, x, y, batch, mc_idx, m_mc, angle_idx, m, copies, cos_sin, lambda, loss, grad, work,
+                             work_bytes, stream);
 }
 
 }  // extern "C"

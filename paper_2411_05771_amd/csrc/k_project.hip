@@ -24,11 +24,13 @@
 // rounding that grows with the image size; out-of-image taps are clamped onto
 // zero LDS borders instead of being branched around.  Sums are kept in float
 // over aligned 16-line blocks (forward) or a line (B^T) and in double across
-// them, so results do not depend on the launch shape.
+// them; the forward residual jobs (y - A x) add every line in double.  So
+// results do not depend on the launch shape.
 //
 // Workgroups are mapped XCD-major: consecutive work items (same image) go to
 // the same XCD, so each XCD's L2 holds only its share of the images.
 #include <algorithm>
+#include <type_traits>
 
 #include "skei_internal.h"
 #include "work.h"
@@ -266,7 +268,8 @@ __device__ __forceinline__ void zero_tail(float *buf, int pitch, int R, int Rc)
 
 // ---------------------------------------------------------------------------
 // KIND kFwd: y[b][r][k] = (1/w) sum_M lerp(line_M, u(k, M))       (Joseph A_S)
-//   resid jobs: y = yfull[b][idx[r]][k] - that, in double.
+//   resid jobs: y = yfull[b][idx[r]][k] - that, in double, with each line's
+//   lerp added in double.
 // KIND kBpT: q[b][r][k] = sum_M sum_j Lambda(w (j - u(k, M))) line_M[j]    (B_S^T)
 //   The pixels within unit distance of the ray in s are the entries within
 //   1/w <= sqrt(2) of u.  With j1 = round(u) and g = u - j1 in [-1/2, 1/2),
@@ -405,46 +408,64 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
                 const float *chunk = lds;
                 // units of this chunk that the wave marches (M0 and ulo are multiples of U)
                 const int ub = max(ulo, M0), ue = min(hi, M0 + Rc - 1);
-                for (int Mb = ub; Mb <= ue; Mb += U) {
-                    // entry j of line Mb + l sits at index j + kBias of `line`
-                    const float *ubase = chunk + (Mb - M0) * pitch + kLinePad - kBias;
+                // PRECISE (the forward residual jobs): every line's interpolated
+                // value is added in double.  The data-consistency residual
+                // y - A x is ~1 % of y, so float block sums of A x would carry
+                // an error ~100x larger relative to the residual.
+                auto march = [&](auto precise_tag) {
+                    constexpr bool PRECISE = decltype(precise_tag)::value;
+                    for (int Mb = ub; Mb <= ue; Mb += U) {
+                        // entry j of line Mb + l sits at index j + kBias of `line`
+                        const float *ubase = chunk + (Mb - M0) * pitch + kLinePad - kBias;
 #pragma unroll
-                    for (int l = 0; l < U; l++) {
-                        const float *line = ubase + l * pitch;
-#pragma unroll
-                        for (int q = 0; q < RPT; q++) {
-                            const unsigned jb = min((unsigned)(int)(u[q] >> 32), cap);
-                            const float fi = (float)(uint32_t)u[q];   // fraction x 2^32
-                            u[q] += du[q];
-                            if constexpr (KIND == kFwd) {
-                                const float t0 = line[jb], t1 = line[jb + 1];
-                                s0[q] += t0;
-                                s1[q] = fmaf(fi, t1 - t0, s1[q]);
-                            } else {
-                                const float *e = line + jb - 1;
-                                // the clamps fold into the FMAs (weights are <= 1)
-                                const float wm = __builtin_amdgcn_fmed3f(fmaf(-fi, wg[q], cm[q]), 0.0f, 1.0f);
-                                const float w0 = 1.0f - fabsf(fmaf(fi, wg[q], hw[q]));
-                                const float wp = __builtin_amdgcn_fmed3f(fmaf(fi, wg[q], cp[q]), 0.0f, 1.0f);
-                                float ls = wm * e[0];
-                                ls = fmaf(w0, e[1], ls);
-                                ls = fmaf(wp, e[2], ls);
-                                accd[q] += (double)ls;
-                            }
-                        }
-                    }
-                    if constexpr (KIND == kFwd) {
-                        // float sums over fixed, aligned 16-line blocks: the rounding
-                        // does not depend on chunking, grouping or launch shape
-                        if (((Mb + U) & 15) == 0) {
+                        for (int l = 0; l < U; l++) {
+                            const float *line = ubase + l * pitch;
 #pragma unroll
                             for (int q = 0; q < RPT; q++) {
-                                accd[q] += fma((double)s1[q], (double)kTwoM32, (double)s0[q]);
-                                s0[q] = 0.0f;
-                                s1[q] = 0.0f;
+                                const unsigned jb = min((unsigned)(int)(u[q] >> 32), cap);
+                                const float fi = (float)(uint32_t)u[q];   // fraction x 2^32
+                                u[q] += du[q];
+                                if constexpr (KIND == kFwd && PRECISE) {
+                                    const float t0 = line[jb], t1 = line[jb + 1];
+                                    accd[q] += (double)fmaf(fi * kTwoM32, t1 - t0, t0);
+                                } else if constexpr (KIND == kFwd) {
+                                    const float t0 = line[jb], t1 = line[jb + 1];
+                                    s0[q] += t0;
+                                    s1[q] = fmaf(fi, t1 - t0, s1[q]);
+                                } else {
+                                    const float *e = line + jb - 1;
+                                    // the clamps fold into the FMAs (weights are <= 1)
+                                    const float wm = __builtin_amdgcn_fmed3f(fmaf(-fi, wg[q], cm[q]), 0.0f, 1.0f);
+                                    const float w0 = 1.0f - fabsf(fmaf(fi, wg[q], hw[q]));
+                                    const float wp = __builtin_amdgcn_fmed3f(fmaf(fi, wg[q], cp[q]), 0.0f, 1.0f);
+                                    float ls = wm * e[0];
+                                    ls = fmaf(w0, e[1], ls);
+                                    ls = fmaf(wp, e[2], ls);
+                                    accd[q] += (double)ls;
+                                }
+                            }
+                        }
+                        if constexpr (KIND == kFwd && !PRECISE) {
+                            // float sums over fixed, aligned 16-line blocks: the rounding
+                            // does not depend on chunking, grouping or launch shape
+                            if (((Mb + U) & 15) == 0) {
+#pragma unroll
+                                for (int q = 0; q < RPT; q++) {
+                                    accd[q] += fma((double)s1[q], (double)kTwoM32, (double)s0[q]);
+                                    s0[q] = 0.0f;
+                                    s1[q] = 0.0f;
+                                }
                             }
                         }
                     }
+                };
+                if constexpr (KIND == kFwd) {
+                    if (resid)
+                        march(std::true_type{});
+                    else
+                        march(std::false_type{});
+                } else {
+                    march(std::false_type{});
                 }
                 __syncthreads();   // the chunk is marched before the next one lands
             }

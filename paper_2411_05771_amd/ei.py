@@ -18,7 +18,6 @@ from __future__ import annotations
 
 import ctypes
 
-import numpy as np
 import torch
 
 from . import capi, ops
@@ -84,9 +83,10 @@ class EIStep:
 def ei_loss_autograd(x, y, geom: ops.Geometry, sketch, cos_sin, lam: float = 1.0, mc=None):
     """The same loss assembled from the differentiable operators.
 
-    x: [B,N,N] (requires_grad as needed); y: [B,N_theta,N_det].  Row selection,
+    x: [B,N,N] (requires_grad as needed); y: [B,N_theta,N_det].  The EI
     subtraction and the sums of squares are torch glue; every operator
-    (A_mc, T, A_S, fbp_S and their transposes in backward) is a library call.
+    (the MC residual y[mc] - A_mc x, T, A_S, fbp_S and their transposes in
+    backward) is a library call.
     """
     sk = ops._as_sketch(geom, sketch)
     mcs = ops._as_sketch(geom, mc)
@@ -95,7 +95,7 @@ def ei_loss_autograd(x, y, geom: ops.Geometry, sketch, cos_sin, lam: float = 1.0
     y3 = y.unsqueeze(0) if y.dim() == 2 else y
     b, n = x3.shape[0], geom.n
     c = cs.shape[0]
-    r_mc = y3[:, torch.from_numpy(mcs.host.astype(np.int64)).to(y3.device)] - ops.radon_fwd(x3, geom, mcs)
+    r_mc = ops.radon_resid(x3, y3, geom, mcs)   # the difference is taken in double
     z = ops.rotate(x3, cs).reshape(b * c, n, n)
     w = ops.fbp(ops.radon_fwd(z, geom, sk), geom, sk)
     r = z - w

@@ -142,6 +142,19 @@ def radon_fwd_(geom: Geometry, x: torch.Tensor, sk: Sketch, out: torch.Tensor | 
     return y if x.dim() == 3 else y[0]
 
 
+def radon_resid_(geom: Geometry, x: torch.Tensor, y_full: torch.Tensor, sk: Sketch,
+                 out: torch.Tensor | None = None) -> torch.Tensor:
+    """S y - A_S x with the projection and the difference in double (skei_radon_resid)."""
+    x3 = _img(geom, x)
+    b = x3.shape[0]
+    y3 = _sino(geom, y_full, geom.n_angles, "y_full")
+    if y3.shape[0] != b:
+        raise ValueError("y_full and x must have the same batch")
+    r = torch.empty((b, sk.m, geom.n_det), device=geom.device, dtype=torch.float32) if out is None else out
+    capi.call("skei_radon_resid", geom.handle, _ptr(x3), _ptr(y3), b, _ptr(sk.dev), sk.m, _ptr(r), _stream())
+    return r if x.dim() == 3 else r[0]
+
+
 def radon_adj_(geom: Geometry, y: torch.Tensor, sk: Sketch, out: torch.Tensor | None = None) -> torch.Tensor:
     y3 = _sino(geom, y, sk.m)
     b = y3.shape[0]
@@ -179,22 +192,31 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
 
 
-def fbp_(geom: Geometry, y: torch.Tensor, sk: Sketch) -> torch.Tensor:
+def _fbp_work(geom: Geometry, b: int, m: int, work: torch.Tensor | None):
+    nb = int(capi.query("skei_fbp_workspace_bytes", geom.handle, b, m))
+    if work is None:
+        return _workspace(nb, geom.device), nb
+    if work.device != geom.device or work.numel() * work.element_size() < nb:
+        raise ValueError(f"fbp workspace must hold {nb} bytes on {geom.device}")
+    return work, work.numel() * work.element_size()
+
+
+def fbp_(geom: Geometry, y: torch.Tensor, sk: Sketch, out: torch.Tensor | None = None,
+         work: torch.Tensor | None = None) -> torch.Tensor:
     y3 = _sino(geom, y, sk.m)
     b = y3.shape[0]
-    x = torch.empty((b, geom.n, geom.n), device=geom.device, dtype=torch.float32)
-    nb = capi.query("skei_fbp_workspace_bytes", geom.handle, b, sk.m)
-    w = _workspace(nb, geom.device)
+    x = torch.empty((b, geom.n, geom.n), device=geom.device, dtype=torch.float32) if out is None else out
+    w, nb = _fbp_work(geom, b, sk.m, work)
     capi.call("skei_fbp", geom.handle, _ptr(y3), b, _ptr(sk.dev), sk.m, _ptr(x), _ptr(w), nb, _stream())
     return x if y.dim() == 3 else x[0]
 
 
-def fbp_adj_(geom: Geometry, x: torch.Tensor, sk: Sketch) -> torch.Tensor:
+def fbp_adj_(geom: Geometry, x: torch.Tensor, sk: Sketch, out: torch.Tensor | None = None,
+             work: torch.Tensor | None = None) -> torch.Tensor:
     x3 = _img(geom, x)
     b = x3.shape[0]
-    y = torch.empty((b, sk.m, geom.n_det), device=geom.device, dtype=torch.float32)
-    nb = capi.query("skei_fbp_workspace_bytes", geom.handle, b, sk.m)
-    w = _workspace(nb, geom.device)
+    y = torch.empty((b, sk.m, geom.n_det), device=geom.device, dtype=torch.float32) if out is None else out
+    w, nb = _fbp_work(geom, b, sk.m, work)
     capi.call("skei_fbp_adj", geom.handle, _ptr(x3), b, _ptr(sk.dev), sk.m, _ptr(y), _ptr(w), nb, _stream())
     return y if x.dim() == 3 else y[0]
 
@@ -259,6 +281,18 @@ class RadonFwd(torch.autograd.Function):
         return radon_adj_(ctx.geom, gy.contiguous(), ctx.sk), None, None
 
 
+class RadonResid(torch.autograd.Function):
+    """r = S y - A_S x; y is data (no gradient), so the backward is -A_S^T."""
+    @staticmethod
+    def forward(ctx, x, y_full, geom, sk):
+        ctx.geom, ctx.sk = geom, sk
+        return radon_resid_(geom, x.contiguous(), y_full.contiguous(), sk)
+
+    @staticmethod
+    def backward(ctx, gr):
+        return -radon_adj_(ctx.geom, gr.contiguous(), ctx.sk), None, None, None
+
+
 class RadonAdj(torch.autograd.Function):
     @staticmethod
     def forward(ctx, y, geom, sk):
@@ -307,6 +341,11 @@ class Rotate(torch.autograd.Function):
 def radon_fwd(x, geom: Geometry, idx=None):
     """A_S x (differentiable)."""
     return RadonFwd.apply(x, geom, _as_sketch(geom, idx))
+
+
+def radon_resid(x, y_full, geom: Geometry, idx=None):
+    """S y - A_S x (differentiable in x; y_full is the whole sinogram)."""
+    return RadonResid.apply(x, y_full, geom, _as_sketch(geom, idx))
 
 
 def radon_adj(y, geom: Geometry, idx=None):

@@ -18,7 +18,7 @@ def declared():
 
 def test_header_declares_the_expected_boundary():
     names = declared()
-    for must in ("skei_geom_create", "skei_radon_fwd", "skei_radon_adj", "skei_fbp", "skei_fbp_adj",
+    for must in ("skei_geom_create", "skei_radon_fwd", "skei_radon_adj", "skei_radon_resid", "skei_fbp", "skei_fbp_adj",
                  "skei_rotate", "skei_rotate_adj", "skei_ei_loss_grad", "skei_strerror"):
         assert must in names
 

@@ -75,6 +75,22 @@ def test_radon_fwd(case):
     assert e < TOL
 
 
+def test_radon_resid(case):
+    """S y - A_S x (the MC residual of the EI loss) against the oracle.  y is
+    A x plus 1 % noise, so the residual is ~100x smaller than y: the bar
+    relative to max |residual| holds only if the projection and the
+    difference are carried in double before the float rounding."""
+    ops, orc = case["ops"], case["orc"]
+    x = f32(case["x"])
+    y_clean = orc.radon_fwd(x, case["na"], case["nd"])
+    y_full = f32(synth.add_relative_noise(y_clean, synth.std_noise(y_clean.shape, synth.SEED_NOISE + 9)))
+    r = ops.radon_resid_(case["geom"], to_dev(x), to_dev(y_full), case["sk"])
+    want = y_full[:, case["idx"]] - orc.radon_fwd(x, case["na"], case["nd"], case["idx"])
+    e = relerr(host(r), want)
+    print(f"radon_resid relerr {e:.3e} (max|r| / max|y| = {np.abs(want).max() / np.abs(y_full).max():.2e})")
+    assert e < TOL
+
+
 def test_radon_adj(case):
     ops, orc = case["ops"], case["orc"]
     ysino = orc.radon_fwd(f32(case["x"]), case["na"], case["nd"], case["idx"])
