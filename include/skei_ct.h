@@ -61,7 +61,9 @@ enum {
     SKEI_ENOMEM = -2,   /* device allocation failed (geometry / plans only)   */
     SKEI_ELAUNCH = -3,  /* a HIP launch or runtime call failed                */
     SKEI_ERANGE = -4,   /* size beyond what the kernels support               */
-    SKEI_ESPACE = -5    /* caller workspace smaller than the *_bytes() query  */
+    SKEI_ESPACE = -5,   /* caller workspace smaller than the *_bytes() query  */
+    SKEI_ESCRATCH = -6  /* need beyond the static scratch of a no-allocation  */
+                        /* entry point                                        */
 };
 
 typedef struct skei_geom skei_geom;
@@ -187,6 +189,29 @@ int skei_ei_loss_grad(const skei_geom *g, const float *x, const float *y, int ba
                       const int32_t *mc_idx, int m_mc, const int32_t *angle_idx, int m,
                       int copies, const float *cos_sin, float lambda,
                       double *loss, float *grad, void *work, size_t work_bytes, void *stream);
+
+/* No-allocation variant of skei_ei_loss_grad, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, results
+ * (bitwise) and kernels as skei_ei_loss_grad, without `work`: the
+ * workspace is a static device array of skei_ei_noalloc_scratch_bytes()
+ * bytes (64 MiB) inside the library, one per device, held from the first
+ * use on that device until the process ends.  The call allocates nothing:
+ * no hipMalloc/hipFree, no allocating library routine.  Its first call on
+ * a device looks up the array's device address (hipGetSymbolAddress) and
+ * caches it.  Limits and errors: SKEI_ESCRATCH (nothing enqueued) when
+ * skei_ei_workspace_bytes() of the arguments exceeds the array, e.g. the
+ * 256 x 256 / 360-angle / 363-detector step with 16 copies and m = 90
+ * needs about 29 MB and fits; a 1024 x 1024 one with 16 copies does not.
+ * Every call on a device shares that device's array and leaves its
+ * contents behind (the step writes every piece before reading it, so
+ * nothing needs clearing): calls that overlap in time on one device, on
+ * any streams, race and must be serialised by the caller. */
+size_t skei_ei_noalloc_scratch_bytes(void);
+int skei_ei_loss_grad_noalloc(const skei_geom *g, const float *x, const float *y, int batch,
+                              const int32_t *mc_idx, int m_mc, const int32_t *angle_idx, int m,
+                              int copies, const float *cos_sin, float lambda,
+                              double *loss, float *grad, void *stream);
 
 /* ------------------------------------------------------------------ */
 /* Batched EI plans: many EI problems of different sizes (own geometry, */

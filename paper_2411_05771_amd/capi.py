@@ -62,6 +62,9 @@ _SIGS = {
     "skei_probe_set": (c_int, [c_int, c_void_p, c_void_p]),
     "skei_ei_loss_grad": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_int, c_void_p, c_int,
                                   c_int, c_void_p, c_float, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "skei_ei_noalloc_scratch_bytes": (c_size_t, []),
+    "skei_ei_loss_grad_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_int, c_void_p, c_int,
+                                          c_int, c_void_p, c_float, c_void_p, c_void_p, c_void_p]),
     "skei_ei_plan_workspace_bytes": (c_size_t, [_PROB, c_int]),
     "skei_ei_problem_workspace_bytes": (c_size_t, [_PROB]),
     "skei_ei_plan_create": (c_int, [_PROB, c_int, c_void_p, c_size_t, ctypes.POINTER(c_void_p)]),

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "ei_step.h"
 #include "skei_internal.h"
@@ -197,6 +198,32 @@ int ei_problem_jobs(const skei_ei_problem &p, const EiBuffers &b, const RayChoic
     return SKEI_OK;
 }
 
+// Scratch of the no-allocation EI entry point: a file-scope device array,
+// so the call itself allocates nothing (for callers that cannot allocate:
+// graph capture, tight serving loops).  Each device that loads the library
+// holds its own copy until the process ends.  In host code `scratch` is
+// only a stand-in for the symbol; its device address on the current device
+// comes from hipGetSymbolAddress, looked up once per device and cached.
+constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+int noalloc_scratch(void **out)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SKEI_ELAUNCH;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return SKEI_ELAUNCH;
+        addr[dev] = ptr;
+    }
+    *out = addr[dev];
+    return SKEI_OK;
+}
+
 int ei_loss_grad_impl(const skei_geom *g, const float *x, const float *y, int batch, const int32_t *mc_idx,
                       int m_mc, const int32_t *angle_idx, int m, int copies, const float *cos_sin, float lambda,
                       double *loss, float *grad, void *work, size_t work_bytes, void *stream)
@@ -383,6 +410,21 @@ int skei_ei_loss_grad(const skei_geom *g, const float *x, const float *y, int ba
 {
     return ei_loss_grad_impl(g, x, y, batch, mc_idx, m_mc, angle_idx, m, copies, cos_sin, lambda, loss, grad, work,
                              work_bytes, stream);
+}
+
+size_t skei_ei_noalloc_scratch_bytes(void) { return kNoallocScratchBytes; }
+
+int skei_ei_loss_grad_noalloc(const skei_geom *g, const float *x, const float *y, int batch, const int32_t *mc_idx,
+                              int m_mc, const int32_t *angle_idx, int m, int copies, const float *cos_sin,
+                              float lambda, double *loss, float *grad, void *stream)
+{
+    if (!g || batch <= 0 || m_mc <= 0 || m <= 0 || copies <= 0) return SKEI_EINVAL;
+    if (ei_workspace_bytes(g, batch, m_mc, m, copies) > kNoallocScratchBytes) return SKEI_ESCRATCH;
+    void *work = nullptr;
+    int rc = noalloc_scratch(&work);
+    if (rc) return rc;
+    return ei_loss_grad_impl(g, x, y, batch, mc_idx, m_mc, angle_idx, m, copies, cos_sin, lambda, loss, grad, work,
+                             kNoallocScratchBytes, stream);
 }
 
 }  // extern "C"

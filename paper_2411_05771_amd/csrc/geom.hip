@@ -59,6 +59,7 @@ const char *skei_strerror(int code)
     case SKEI_ELAUNCH: return "HIP launch or runtime call failed";
     case SKEI_ERANGE: return "size beyond the supported range";
     case SKEI_ESPACE: return "workspace smaller than required";
+    case SKEI_ESCRATCH: return "workspace need exceeds the static scratch of the no-allocation entry point";
     default: return "unknown error";
     }
 }
