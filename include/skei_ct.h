@@ -269,7 +269,8 @@ int skei_ei_plan_run(skei_ei_plan *plan, void *stream);
  * `shape`: for the ray-driven stages (FWD, BP_T) rays per thread (1..4)
  * plus 100 x the image lines per march unit (0 = built-in, 4, 8 or 16; an
  * LDS chunk holds two units), plus 10000 for workgroups of three waves
- * instead of four, plus 20000 for LDS chunks of four units;
+ * instead of four, plus 20000 for LDS chunks of four units, plus 40000 for
+ * six waves or 80000 for eight waves (one or two rays per thread);
  * for the gathers (BP_RESID, ADJ) angle groups per pixel (1, 2, 4) with one
  * pixel per thread, or 10 x groups + 4 (14, 24, 44) with four pixels per
  * thread; 0 keeps the default; ignored by the other stages.  Synchronises the device when
@@ -312,6 +313,17 @@ enum {
     SKEI_STAGE_ROTATE_ADJ = 8, SKEI_STAGE_COUNT = 9
 };
 int skei_probe_set(int stage, void *ev_begin, void *ev_end);
+
+/* Layout self-check (host only, no device work): walks every LDS read a
+ * kernel makes, from the kernel's own layout formulas, for one size.
+ *   SKEI_LDS_RAMP, size = N_det (2..2048): out[0..4] = lowest element read,
+ *     highest read by a thread that owns an output, highest read by any
+ *     thread, last element of the staged row, elements allocated (doubles).
+ *   SKEI_LDS_RAY, size = N (2..2032): out[0..2] = lowest and highest
+ *     position read within a staged image line, and the line pitch (floats).
+ * Returns SKEI_EINVAL / SKEI_ERANGE for a bad kernel or size. */
+enum { SKEI_LDS_RAMP = 0, SKEI_LDS_RAY = 1 };
+int skei_lds_read_bounds(int kernel, int size, long long *out);
 
 #ifdef __cplusplus
 }

@@ -62,6 +62,7 @@ _SIGS = {
     "skei_probe_set": (c_int, [c_int, c_void_p, c_void_p]),
     "skei_ei_loss_grad": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_int, c_void_p, c_int,
                                   c_int, c_void_p, c_float, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "skei_lds_read_bounds": (c_int, [c_int, c_int, ctypes.POINTER(ctypes.c_longlong)]),
     "skei_ei_noalloc_scratch_bytes": (c_size_t, []),
     "skei_ei_loss_grad_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_int, c_void_p, c_int,
                                           c_int, c_void_p, c_float, c_void_p, c_void_p, c_void_p]),

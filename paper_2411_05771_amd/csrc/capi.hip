@@ -137,9 +137,18 @@ int ei_problem_jobs(const skei_ei_problem &p, const EiBuffers &b, const RayChoic
     J.rot[0] = make_rot_job(p.x, batch, copies, n, p.cos_sin, b.z, b.zT);
     J.rot[1] = make_rot_job(p.x, batch, 1, n, nullptr, nullptr, b.xT);
     RayTune tf = g->tune_fwd, tb = g->tune_bpt;
-    // built-in chunk height of both ray stages: 8 lines (higher occupancy)
-    if (tf.lines == 0) tf.lines = 8;
-    if (tb.lines == 0) tb.lines = 8;
+    // built-in march units when the geometry is not tuned: 8 lines (forward)
+    // and 4 lines (B^T), four units per LDS chunk for images up to 512 (the
+    // autotuner's MI355X choice at 256 x 256), two above (occupancy)
+    const int units = n <= 512 ? 4 : 2;
+    if (tf.lines == 0) {
+        tf.lines = 8;
+        tf.units = units;
+    }
+    if (tb.lines == 0) {
+        tb.lines = n <= 512 ? 4 : 8;
+        tb.units = units;
+    }
     if (!fwd.own) {
         tf = RayTune{};
         tf.lines = fwd.lines;
@@ -273,6 +282,22 @@ int ei_loss_grad_impl(const skei_geom *g, const float *x, const float *y, int ba
 }  // namespace skei
 
 extern "C" {
+
+int skei_lds_read_bounds(int kernel, int size, long long *out)
+{
+    if (!out || size < 2) return SKEI_EINVAL;
+    if (kernel == SKEI_LDS_RAMP) {
+        if (size > 2048) return SKEI_ERANGE;
+        ramp_lds_reads(size, out);
+        return SKEI_OK;
+    }
+    if (kernel == SKEI_LDS_RAY) {
+        if (size > 2032) return SKEI_ERANGE;
+        ray_lds_reads(size, out);
+        return SKEI_OK;
+    }
+    return SKEI_EINVAL;
+}
 
 int skei_probe_set(int stage, void *ev_begin, void *ev_end)
 {

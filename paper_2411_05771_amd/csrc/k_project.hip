@@ -23,14 +23,17 @@
 // (u(k, M+1) = u(k, M) + du), so the interpolation position carries no
 // rounding that grows with the image size; out-of-image taps are clamped onto
 // zero LDS borders instead of being branched around.  Sums are kept in float
-// over aligned 16-line blocks (forward) or a line (B^T) and in double across
-// them; the forward residual jobs (y - A x) add every line in double.  So
-// results do not depend on the launch shape.
+// over aligned 16-line blocks and in double across them; the forward
+// residual jobs (y - A x) use aligned 4-line float sums.  So results do not
+// depend on the launch shape.
+//
+// In B^T a wave's rays come in blocks of 64 consecutive detectors, and each
+// block marches only the lines its rays cross: rays near the edge of an
+// angle's image shadow cross few lines.
 //
 // Workgroups are mapped XCD-major: consecutive work items (same image) go to
 // the same XCD, so each XCD's L2 holds only its share of the images.
 #include <algorithm>
-#include <type_traits>
 
 #include "skei_internal.h"
 #include "work.h"
@@ -41,7 +44,7 @@ namespace {
 typedef __attribute__((address_space(1))) const void gmem_t;
 typedef __attribute__((address_space(3))) void lmem_t;
 
-constexpr int kMaxWaves = 4;                 // waves per workgroup: 3 or 4
+constexpr int kMaxWaves = 8;                 // waves per workgroup: 3, 4, 6 or 8
 constexpr int kMaxG = 8;                     // listed angles per workgroup
 constexpr int kMaxRpt = 4;                   // rays per thread
 constexpr size_t kLdsBudget = 40 * 1024;     // staging buffer (default)
@@ -54,6 +57,29 @@ enum Kind : int { kFwd = 0, kBpT = 1 };
 int line_pitch(int n) { return ((n + 2 * kLinePad) + 3) & ~3; }
 
 }  // namespace
+
+// Host walk of the tap positions the march reads within a staged line of an
+// n-pixel image, for both kinds, from the kernel's bias and clamp constants:
+// out = {lowest position, highest position, line pitch}.  Tap indices are
+// clamped to [0, n + 1 + bias] by one unsigned min; positions beyond the
+// image land on the zeroed pads.
+void ray_lds_reads(int n, long long out[3])
+{
+    long long lo = 1LL << 60, hi = -1;
+    for (int kind = 0; kind < 2; kind++) {
+        const int bias = kind == kFwd ? kLinePad : kLinePad - 1;   // kBias of ray_item
+        const long long cap = n + 1 + bias;
+        const long long base = kLinePad - bias;   // `line` = start of the staged line + base
+        const int first = kind == kFwd ? 0 : -1, taps = kind == kFwd ? 2 : 3;
+        for (long long jb : {0LL, cap}) {
+            lo = std::min(lo, base + jb + first);
+            hi = std::max(hi, base + jb + first + taps - 1);
+        }
+    }
+    out[0] = lo;
+    out[1] = hi;
+    out[2] = line_pitch(n);
+}
 
 int make_ray_job(const skei_geom *g, const float *x, const float *xT, int batch, const int32_t *idx, int m, void *y,
                  const float *yfull, const RayTune &t, int rpt_cap, RayJob &J, RayShape &shape)
@@ -81,7 +107,7 @@ int make_ray_job(const skei_geom *g, const float *x, const float *xT, int batch,
         const int rays = G * ((nd + nseg - 1) / nseg);
         return (double)rays / (double)(((rays + block - 1) / block) * block);
     };
-    int G, nseg, waves = t.waves == 3 ? 3 : 4;
+    int G, nseg, waves = (t.waves == 3 || t.waves == 6 || t.waves == 8) ? t.waves : 4;
     double fill = layout(waves, G, nseg);
     if (t.waves == 0) {
         // automatic: three waves when they leave fewer ray slots empty
@@ -134,7 +160,7 @@ int make_ray_job(const skei_geom *g, const float *x, const float *xT, int batch,
     shape.rpt = (G * J.seg + block - 1) / block;
     shape.waves = waves;
     shape.shm = (size_t)J.R * J.pitch * sizeof(float);
-    if (shape.shm > kLdsMax || shape.rpt > kMaxRpt) return SKEI_ERANGE;
+    if (shape.shm > kLdsMax || shape.rpt > (waves > 4 ? 2 : kMaxRpt)) return SKEI_ERANGE;
     return SKEI_OK;
 }
 
@@ -268,8 +294,8 @@ __device__ __forceinline__ void zero_tail(float *buf, int pitch, int R, int Rc)
 
 // ---------------------------------------------------------------------------
 // KIND kFwd: y[b][r][k] = (1/w) sum_M lerp(line_M, u(k, M))       (Joseph A_S)
-//   resid jobs: y = yfull[b][idx[r]][k] - that, in double, with each line's
-//   lerp added in double.
+//   resid jobs: y = yfull[b][idx[r]][k] - that, in double, with the lerps of
+//   each aligned group of 4 lines summed in float and the groups in double.
 // KIND kBpT: q[b][r][k] = sum_M sum_j Lambda(w (j - u(k, M))) line_M[j]    (B_S^T)
 //   The pixels within unit distance of the ray in s are the entries within
 //   1/w <= sqrt(2) of u.  With j1 = round(u) and g = u - j1 in [-1/2, 1/2),
@@ -316,16 +342,30 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
     __syncthreads();
     const float *img = x + (size_t)b * n * n;
 
-    // Ray slot of (thread, q): blocks of 32 consecutive detectors are dealt
-    // round-robin to the waves, so every wave spans the whole detector range
-    // and marches the same lines (no wave idles at the chunk barriers), and
-    // each half-wave reads one contiguous run of LDS entries.
+    // Ray slot of (thread, q).
+    //  - B^T: the item's rays are cut into blocks of 64 consecutive (angle,
+    //    detector) rays, one per (wave, q); lane l holds ray l of its block.
+    //    Each (wave, q) block marches only the lines its own rays cross, so
+    //    rays near the edge of an angle's shadow cost few lines.  Blocks are
+    //    dealt boustrophedon (wave w takes blocks w, 2W-1-w, 2W+w, ...), which
+    //    pairs an edge block with a central one in every wave.
+    //  - Forward: blocks of 32 consecutive detectors are dealt round-robin to
+    //    the waves, so every wave spans the whole detector range and marches
+    //    the same lines, with a lane's RPT rays interleaved line by line (the
+    //    forward tap is cheap, and marching the rays together shares the
+    //    loop's scalar work between them).
     int rg[RPT], rk[RPT];
     double accd[RPT];
-    const int slot0 = (tid & 31) + 32 * ((tid >> 6) + kWaves * ((tid & 63) >> 5));
+    const int wave_id = tid >> 6, lane = tid & 63;
 #pragma unroll
     for (int q = 0; q < RPT; q++) {
-        const int t = slot0 + q * kBlock;
+        int t;
+        if constexpr (KIND == kFwd) {
+            t = (lane & 31) + 32 * (wave_id + kWaves * (lane >> 5)) + q * kBlock;
+        } else {
+            const int blk = (q & 1) ? (q + 1) * kWaves - 1 - wave_id : q * kWaves + wave_id;
+            t = 64 * blk + lane;
+        }
         const bool valid = t < gcount * k_len;
         rg[q] = valid ? t / k_len : -1;
         rk[q] = valid ? k_begin + (t - rg[q] * k_len) : 0;
@@ -342,17 +382,27 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
         // the image with a zero step: they read zero borders and add nothing.
         int64_t u[RPT], du[RPT];
         float s0[RPT], s1[RPT], wg[RPT], cm[RPT], cp[RPT], hw[RPT];
-        int lo = n, hi = -1;
+        // line range of each ray; B^T keeps one per block (q), the forward
+        // only the wave's union
+        int lo[KIND == kFwd ? 1 : RPT], hi[KIND == kFwd ? 1 : RPT];
+        lo[0] = n;
+        hi[0] = -1;
 #pragma unroll
         for (int q = 0; q < RPT; q++) {
             const int gq = rg[q] < 0 ? 0 : rg[q];
             const AngleRow &A = ang[gq];
             const bool act = rg[q] >= 0 && A.rows == pass;
-            if (act) {
-                int l0, h0;
-                ray_range(fmaf((float)rk[q], A.inv_m, A.base), A.du, n, l0, h0);
-                lo = min(lo, l0);
-                hi = max(hi, h0);
+            if constexpr (KIND == kFwd) {
+                if (act) {
+                    int l0, h0;
+                    ray_range(fmaf((float)rk[q], A.inv_m, A.base), A.du, n, l0, h0);
+                    lo[0] = min(lo[0], l0);
+                    hi[0] = max(hi[0], h0);
+                }
+            } else {
+                lo[q] = n;
+                hi[q] = -1;
+                if (act) ray_range(fmaf((float)rk[q], A.inv_m, A.base), A.du, n, lo[q], hi[q]);
             }
             // biased by kBias entries so that tap indices are non-negative
             // inside the padded line; one unsigned min clamps both ends
@@ -370,11 +420,19 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
             cp[q] = 1.0f - 1.5f * A.w;
             hw[q] = -0.5f * A.w;
         }
-        lo = __builtin_amdgcn_readfirstlane(wave_min(lo));
-        hi = __builtin_amdgcn_readfirstlane(wave_max(hi));
-        if ((tid & 63) == 0) {
-            wrange[0][tid >> 6] = lo;
-            wrange[1][tid >> 6] = hi;
+        // each block's lines (wave-uniform), and the wave's union
+        constexpr int kRanges = KIND == kFwd ? 1 : RPT;
+        int wlo = n, whi = -1;
+#pragma unroll
+        for (int q = 0; q < kRanges; q++) {
+            lo[q] = __builtin_amdgcn_readfirstlane(wave_min(lo[q]));
+            hi[q] = __builtin_amdgcn_readfirstlane(wave_max(hi[q]));
+            wlo = min(wlo, lo[q]);
+            whi = max(whi, hi[q]);
+        }
+        if (lane == 0) {
+            wrange[0][wave_id] = wlo;
+            wrange[1][wave_id] = whi;
         }
         __syncthreads();
         int blo = n, bhi = -1;
@@ -382,11 +440,13 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
             blo = min(blo, wrange[0][w]);
             bhi = max(bhi, wrange[1][w]);
         }
-        // The wave marches whole U-line units, from the unit holding its first
+        // A block marches whole U-line units, from the unit holding its first
         // line; on lines outside a ray's own range the ray reads zero borders.
-        const int ulo = lo & ~(U - 1);
+        int ulo[kRanges];
 #pragma unroll
-        for (int q = 0; q < RPT; q++) u[q] += (int64_t)ulo * du[q];
+        for (int q = 0; q < kRanges; q++) ulo[q] = lo[q] & ~(U - 1);
+#pragma unroll
+        for (int q = 0; q < RPT; q++) u[q] += (int64_t)ulo[KIND == kFwd ? 0 : q] * du[q];
 
         const bool rows = pass == 1;
         // column passes read rows of the transposed image when it is given
@@ -406,48 +466,63 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
                 }
                 __syncthreads();
                 const float *chunk = lds;
-                // units of this chunk that the wave marches (M0 and ulo are multiples of U)
-                const int ub = max(ulo, M0), ue = min(hi, M0 + Rc - 1);
-                // PRECISE (the forward residual jobs): every line's interpolated
-                // value is added in double.  The data-consistency residual
-                // y - A x is ~1 % of y, so float block sums of A x would carry
-                // an error ~100x larger relative to the residual.
-                auto march = [&](auto precise_tag) {
-                    constexpr bool PRECISE = decltype(precise_tag)::value;
-                    for (int Mb = ub; Mb <= ue; Mb += U) {
-                        // entry j of line Mb + l sits at index j + kBias of `line`
-                        const float *ubase = chunk + (Mb - M0) * pitch + kLinePad - kBias;
+                // Forward residual jobs sum the interpolated values of each
+                // aligned group of 4 lines in float and the groups in double:
+                // the data-consistency residual y - A x is ~1 % of y, so the
+                // 16-line float block sums of A x would carry an error ~100x
+                // larger relative to the residual.  Every grouping is fixed and
+                // aligned, so the rounding does not depend on chunking or launch
+                // shape.
+                if constexpr (KIND == kFwd) {
+                    // every ray of the wave over the wave's lines, RPT rays
+                    // interleaved per line (M0 and ulo are multiples of U)
+                    const int ub = max(ulo[0], M0), ue = min(whi, M0 + Rc - 1);
+                    if (resid) {
+                        // residual jobs: each line's lerp in float, four lines
+                        // (aligned) summed in float, then added in double; the
+                        // groups are not unrolled, so this loop needs no more
+                        // registers than the one below
+#pragma unroll 1
+                        for (int Mb = ub; Mb <= ue; Mb += U) {
+                            // entry j of line Mb + l sits at index j + kBias of `line`
+                            const float *ubase = chunk + (Mb - M0) * pitch + kLinePad - kBias;
+#pragma unroll 1
+                            for (int l4 = 0; l4 < U; l4 += 4) {
+                                float v4[RPT];
 #pragma unroll
-                        for (int l = 0; l < U; l++) {
-                            const float *line = ubase + l * pitch;
+                                for (int l = l4; l < l4 + 4; l++) {
+                                    const float *line = ubase + l * pitch;
 #pragma unroll
-                            for (int q = 0; q < RPT; q++) {
-                                const unsigned jb = min((unsigned)(int)(u[q] >> 32), cap);
-                                const float fi = (float)(uint32_t)u[q];   // fraction x 2^32
-                                u[q] += du[q];
-                                if constexpr (KIND == kFwd && PRECISE) {
-                                    const float t0 = line[jb], t1 = line[jb + 1];
-                                    accd[q] += (double)fmaf(fi * kTwoM32, t1 - t0, t0);
-                                } else if constexpr (KIND == kFwd) {
+                                    for (int q = 0; q < RPT; q++) {
+                                        const unsigned jb = min((unsigned)(int)(u[q] >> 32), cap);
+                                        const float fi = (float)(uint32_t)u[q];   // fraction x 2^32
+                                        u[q] += du[q];
+                                        const float t0 = line[jb], t1 = line[jb + 1];
+                                        const float v = fmaf(fi * kTwoM32, t1 - t0, t0);
+                                        v4[q] = l == l4 ? v : v4[q] + v;
+                                    }
+                                }
+#pragma unroll
+                                for (int q = 0; q < RPT; q++) accd[q] += (double)v4[q];
+                            }
+                        }
+                    } else {
+                        for (int Mb = ub; Mb <= ue; Mb += U) {
+                            const float *ubase = chunk + (Mb - M0) * pitch + kLinePad - kBias;
+#pragma unroll
+                            for (int l = 0; l < U; l++) {
+                                const float *line = ubase + l * pitch;
+#pragma unroll
+                                for (int q = 0; q < RPT; q++) {
+                                    const unsigned jb = min((unsigned)(int)(u[q] >> 32), cap);
+                                    const float fi = (float)(uint32_t)u[q];   // fraction x 2^32
+                                    u[q] += du[q];
                                     const float t0 = line[jb], t1 = line[jb + 1];
                                     s0[q] += t0;
                                     s1[q] = fmaf(fi, t1 - t0, s1[q]);
-                                } else {
-                                    const float *e = line + jb - 1;
-                                    // the clamps fold into the FMAs (weights are <= 1)
-                                    const float wm = __builtin_amdgcn_fmed3f(fmaf(-fi, wg[q], cm[q]), 0.0f, 1.0f);
-                                    const float w0 = 1.0f - fabsf(fmaf(fi, wg[q], hw[q]));
-                                    const float wp = __builtin_amdgcn_fmed3f(fmaf(fi, wg[q], cp[q]), 0.0f, 1.0f);
-                                    float ls = wm * e[0];
-                                    ls = fmaf(w0, e[1], ls);
-                                    ls = fmaf(wp, e[2], ls);
-                                    accd[q] += (double)ls;
                                 }
                             }
-                        }
-                        if constexpr (KIND == kFwd && !PRECISE) {
-                            // float sums over fixed, aligned 16-line blocks: the rounding
-                            // does not depend on chunking, grouping or launch shape
+                            // float sums over fixed, aligned 16-line blocks
                             if (((Mb + U) & 15) == 0) {
 #pragma unroll
                                 for (int q = 0; q < RPT; q++) {
@@ -458,23 +533,64 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
                             }
                         }
                     }
-                };
-                if constexpr (KIND == kFwd) {
-                    if (resid)
-                        march(std::true_type{});
-                    else
-                        march(std::false_type{});
                 } else {
-                    march(std::false_type{});
+#pragma unroll
+                    for (int q = 0; q < RPT; q++) {
+                        // units of this chunk that block q marches (M0 and ulo are multiples of U)
+                        const int qr = KIND == kFwd ? 0 : q;
+                        const int ub = max(ulo[qr], M0), ue = min(hi[qr], M0 + Rc - 1);
+                        // Lines run in units of U inside fixed, aligned 16-line
+                        // blocks; the float block sum goes to double once the
+                        // block's last line is marched.  Each unit runs in two
+                        // phases: every line's tap address and LDS loads first,
+                        // then the weights and sums, so its loads are in flight
+                        // together instead of one line at a time.
+#pragma unroll 1
+                        for (int Bb = ub & ~15; Bb <= ue; Bb += 16) {
+                            const int u1 = min(ue, Bb + 15);
+#pragma unroll 1
+                            for (int Mb = max(ub, Bb); Mb <= u1; Mb += U) {
+                                const float *ubase = chunk + (Mb - M0) * pitch + kLinePad - kBias;
+                                float tap[U][3], fr[U];
+#pragma unroll
+                                for (int l = 0; l < U; l++) {
+                                    const unsigned jb = min((unsigned)(int)(u[q] >> 32), cap);
+                                    fr[l] = (float)(uint32_t)u[q];   // fraction x 2^32
+                                    u[q] += du[q];
+                                    const float *e = ubase + l * pitch + jb - 1;
+#pragma unroll
+                                    for (int t = 0; t < 3; t++) tap[l][t] = e[t];
+                                }
+#pragma unroll
+                                for (int l = 0; l < U; l++) {
+                                    const float fi = fr[l];
+                                    // the clamps fold into the FMAs (weights are <= 1)
+                                    const float wm = __builtin_amdgcn_fmed3f(fmaf(-fi, wg[q], cm[q]), 0.0f, 1.0f);
+                                    const float w0 = 1.0f - fabsf(fmaf(fi, wg[q], hw[q]));
+                                    const float wp = __builtin_amdgcn_fmed3f(fmaf(fi, wg[q], cp[q]), 0.0f, 1.0f);
+                                    s0[q] = fmaf(wm, tap[l][0], s0[q]);
+                                    s0[q] = fmaf(w0, tap[l][1], s0[q]);
+                                    s0[q] = fmaf(wp, tap[l][2], s0[q]);
+                                }
+                            }
+                            if (u1 == Bb + 15) {   // the block is complete
+                                accd[q] += (double)s0[q];
+                                s0[q] = 0.0f;
+                            }
+                        }
+                    }
                 }
                 __syncthreads();   // the chunk is marched before the next one lands
             }
         } else {
             __syncthreads();
         }
-        if constexpr (KIND == kFwd) {
 #pragma unroll
-            for (int q = 0; q < RPT; q++) accd[q] += fma((double)s1[q], (double)kTwoM32, (double)s0[q]);
+        for (int q = 0; q < RPT; q++) {
+            if constexpr (KIND == kFwd)
+                accd[q] += fma((double)s1[q], (double)kTwoM32, (double)s0[q]);
+            else
+                accd[q] += (double)s0[q];
         }
     }
 
@@ -504,13 +620,29 @@ __global__ void __launch_bounds__(64 * NW) k_ray(const JobList<RayJob> L)
     for_each_item(L, [&](const RayJob &J, long long item) { ray_item<KIND, RPT, U, OUT, NW>(J, item, lds); });
 }
 
+// The forward projector with a register budget: its residual loop would
+// otherwise raise the whole kernel's allocation (to ~90 VGPRs, 5 waves per
+// SIMD), while the fast march needs ~70; a launch of a few thousand waves
+// then no longer stays resident in one pass (measured 63 -> 75 us at 256^2).
+template <int RPT, int U, int NW>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(RPT <= 2 ? 7 : 1)))
+    k_ray_fwd(const JobList<RayJob> L)
+{
+    extern __shared__ __align__(16) float lds[];
+    for_each_item(L, [&](const RayJob &J, long long item) { ray_item<kFwd, RPT, U, float, NW>(J, item, lds); });
+}
+
 template <int KIND, int RPT, int U, typename OUT, int NW>
 int ray_launch1(size_t shm, const JobList<RayJob> &L, hipStream_t st)
 {
-    const long long grid =
-        launch_grid(L, reinterpret_cast<const void *>(&k_ray<KIND, RPT, U, OUT, NW>), 64 * NW, shm);
+    const void *fn = KIND == kFwd ? reinterpret_cast<const void *>(&k_ray_fwd<RPT, U, NW>)
+                                  : reinterpret_cast<const void *>(&k_ray<KIND, RPT, U, OUT, NW>);
+    const long long grid = launch_grid(L, fn, 64 * NW, shm);
     if (grid <= 0 || grid > 0x7fffffffLL) return SKEI_ERANGE;
-    hipLaunchKernelGGL((k_ray<KIND, RPT, U, OUT, NW>), dim3((unsigned)grid), dim3(64 * NW), shm, st, L);
+    if constexpr (KIND == kFwd)
+        hipLaunchKernelGGL((k_ray_fwd<RPT, U, NW>), dim3((unsigned)grid), dim3(64 * NW), shm, st, L);
+    else
+        hipLaunchKernelGGL((k_ray<KIND, RPT, U, OUT, NW>), dim3((unsigned)grid), dim3(64 * NW), shm, st, L);
     return check_launch();
 }
 
@@ -537,12 +669,37 @@ int ray_launch_w(int rpt, int unroll, size_t shm, const JobList<RayJob> &L, hipS
     }
 }
 
+// Six- and eight-wave workgroups hold one or two rays per thread.
+template <int KIND, typename OUT, int NW>
+int ray_launch_wide(int rpt, int unroll, size_t shm, const JobList<RayJob> &L, hipStream_t st)
+{
+    if (rpt == 1) {
+        switch (unroll) {
+        case 16: return ray_launch1<KIND, 1, 16, OUT, NW>(shm, L, st);
+        case 8: return ray_launch1<KIND, 1, 8, OUT, NW>(shm, L, st);
+        case 4: return ray_launch1<KIND, 1, 4, OUT, NW>(shm, L, st);
+        default: return SKEI_ERANGE;
+        }
+    }
+    if (rpt == 2) {
+        switch (unroll) {
+        case 16: return ray_launch1<KIND, 2, 16, OUT, NW>(shm, L, st);
+        case 8: return ray_launch1<KIND, 2, 8, OUT, NW>(shm, L, st);
+        case 4: return ray_launch1<KIND, 2, 4, OUT, NW>(shm, L, st);
+        default: return SKEI_ERANGE;
+        }
+    }
+    return SKEI_ERANGE;
+}
+
 template <int KIND, typename OUT>
 int ray_launch(const RayShape &sh, const JobList<RayJob> &L, hipStream_t st)
 {
     if (L.total <= 0) return SKEI_OK;
     if (sh.waves == 3) return ray_launch_w<KIND, OUT, 3>(sh.rpt, sh.unroll, sh.shm, L, st);
     if (sh.waves == 4) return ray_launch_w<KIND, OUT, 4>(sh.rpt, sh.unroll, sh.shm, L, st);
+    if (sh.waves == 6) return ray_launch_wide<KIND, OUT, 6>(sh.rpt, sh.unroll, sh.shm, L, st);
+    if (sh.waves == 8) return ray_launch_wide<KIND, OUT, 8>(sh.rpt, sh.unroll, sh.shm, L, st);
     return SKEI_ERANGE;
 }
 

@@ -35,6 +35,12 @@ __device__ __host__ __forceinline__ int ramp_pad(int n_det) { return 2 * ramp_ta
 // the tap index is uniform across every wave
 __device__ __host__ __forceinline__ int ramp_group(int n_det) { return ((n_det + kRampV - 1) / kRampV + 63) / 64 * 64; }
 
+// Skewed-position offsets of the window reads of a 4-tap step (see ramp_item):
+// left reads L[1], L[0] from the left base, right reads R[V-2], R[V-1] from
+// the right base, for each of the step's 4 taps.
+constexpr int kL[4][2] = {{0, -2}, {-3, -4}, {-5, -6}, {-7, -8}};
+constexpr int kR[4][2] = {{3, 4}, {5, 6}, {7, 9}, {10, 11}};
+
 template <typename IN>
 __device__ __forceinline__ void ramp_item(const RampJob &J, long long r, double *row)
 {
@@ -102,8 +108,6 @@ __device__ __forceinline__ void ramp_item(const RampJob &J, long long r, double 
         // elements b + 2u and b + 2u + 1 with b = pad + 2e + 9 = 3 (mod 8):
         // their skewed positions are fixed offsets from 9 a / 8 and 9 (b - 3) / 8,
         // and both bases move by 9 per step, so no read needs address arithmetic.
-        constexpr int kL[4][2] = {{0, -2}, {-3, -4}, {-5, -6}, {-7, -8}};   // L[1], L[0]
-        constexpr int kR[4][2] = {{3, 4}, {5, 6}, {7, 9}, {10, 11}};       // R[V - 2], R[V - 1]
         const double *pl = c + 9 * ((pad - 2 * e0 - 2) >> 3);
         const double *pr = c + 9 * ((pad + 2 * e0 + 9) >> 3);
         for (int e = e0; e < e0 + ES; e += 4, pl -= 9, pr += 9) {
@@ -163,6 +167,50 @@ int ramp_launch(int block, size_t shm, const JobList<RampJob> &L, hipStream_t st
 }  // namespace
 
 int ramp_block(int n_det) { return kRampS * ramp_group(n_det); }
+
+// Host walk of every LDS read ramp_item makes for rows of n_det samples, with
+// the kernel's own layout formulas and offset tables: out = {lowest index,
+// highest index read by a thread that owns an output, highest index read by
+// any thread (idle threads past the row end included), last index of the
+// row area, elements allocated}, all in doubles from the start of the row.
+void ramp_lds_reads(int n_det, long long out[5])
+{
+    constexpr int V = kRampV, S = kRampS;
+    const int E = ramp_taps(n_det), ES = E / S, pad = ramp_pad(n_det), per = ramp_group(n_det);
+    const long long len = n_det + 2LL * pad;
+    long long lo = 1LL << 60, hi_active = -1, hi_any = -1;
+    auto see = [&](long long pos, bool active) {
+        lo = std::min(lo, pos);
+        hi_any = std::max(hi_any, pos);
+        if (active) hi_active = std::max(hi_active, pos);
+    };
+    for (int sg = 0; sg < S; sg++) {
+        const int e0 = sg * ES;
+        for (int t = 0; t < per; t++) {
+            const bool active = t * V < n_det;
+            const long long c = 9LL * t;
+            for (int i = 0; i < V; i++) {
+                for (const int o : {i - 2 * e0 - 1, i + 2 * e0 + 1}) {
+                    const long long q = pad + o;
+                    see(c + q + (q >> 3), active);
+                }
+            }
+            long long pl = c + 9LL * ((pad - 2 * e0 - 2) >> 3), pr = c + 9LL * ((pad + 2 * e0 + 9) >> 3);
+            for (int e = e0; e < e0 + ES; e += 4, pl -= 9, pr += 9)
+                for (int u = 0; u < 4; u++) {
+                    see(pl + kL[u][0], active);
+                    see(pl + kL[u][1], active);
+                    see(pr + kR[u][0], active);
+                    see(pr + kR[u][1], active);
+                }
+        }
+    }
+    out[0] = lo;
+    out[1] = hi_active;
+    out[2] = hi_any;
+    out[3] = (len - 1) + ((len - 1) >> 3);
+    out[4] = (long long)(ramp_shm(n_det) / sizeof(double));
+}
 
 size_t ramp_shm(int n_det)
 {

@@ -46,6 +46,29 @@ struct StageTable {
 };
 
 bool is_ray_stage(int s) { return s == SKEI_STAGE_FWD || s == SKEI_STAGE_BP_T; }
+
+// Ray-stage shape codes (skei_ei_plan_configure): the wave count and chunk
+// flags live in the ten-thousands digits as bits (1: three waves, 2: chunks
+// of four units, 4: six waves, 8: eight waves); 0 waves = automatic.
+int ray_code_waves(int shape)
+{
+    const int f = shape / 10000;
+    return f & 1 ? 3 : f & 4 ? 6 : f & 8 ? 8 : shape > 0 ? 4 : 0;
+}
+bool ray_code_units4(int shape) { return (shape / 10000) & 2; }
+bool ray_code_valid(int shape)
+{
+    const int rpt = shape % 100, lines = shape % 10000 / 100, f = shape / 10000;
+    const int wave_bits = (f & 1) + ((f >> 2) & 1) + ((f >> 3) & 1);
+    if (shape < 0 || f >= 16 || rpt > 4 || wave_bits > 1) return false;
+    if ((f & 12) && rpt > 2) return false;   // six or eight waves: at most 2 rays per thread
+    return lines == 0 || lines == 4 || lines == 8 || lines == 16;
+}
+int ray_code(const RayShape &r, int cfg_shape)
+{
+    return r.rpt + 100 * (cfg_shape % 10000 / 100) + (r.waves == 3 ? 10000 : 0) + (ray_code_units4(cfg_shape) ? 20000 : 0) +
+           (r.waves == 6 ? 40000 : 0) + (r.waves == 8 ? 80000 : 0);
+}
 bool is_gather_stage(int s) { return s == SKEI_STAGE_BP_RESID || s == SKEI_STAGE_ADJ; }
 
 // Host image of the device table: appends `bytes` at a 256-byte boundary.
@@ -113,16 +136,17 @@ int plan_build(skei_ei_plan *P)
     for (const skei_ei_problem &p : P->probs) max_nd = std::max(max_nd, p.geom->n_det);
     const int def_rpt = max_nd > 400 ? 3 : 2;
     // ray-stage shape code: rays per thread + 100 x march unit height, + 10000
-    // for three-wave workgroups, + 20000 for LDS chunks of four units
-    // (both run best with the higher occupancy of 8-line chunks by default;
-    // the default wave count is the first problem's automatic choice)
+    // for three-wave workgroups, + 20000 for LDS chunks of four units, + 40000
+    // for six-wave and + 80000 for eight-wave workgroups (both run best with
+    // the higher occupancy of 8-line chunks by default; the default wave
+    // count is the first problem's automatic choice)
     auto choice = [&](int shape, int def_lines) {
         RayChoice c;
         c.own = false;
         c.rpt = shape % 100 > 0 ? shape % 100 : def_rpt;
         c.lines = shape % 10000 > 0 ? shape % 10000 / 100 : def_lines;
-        c.waves = (shape / 10000) & 1 ? 3 : shape > 0 ? 4 : 0;
-        c.units = shape >= 20000 ? 4 : 2;
+        c.waves = ray_code_waves(shape);
+        c.units = ray_code_units4(shape) ? 4 : 2;
         return c;
     };
     RayChoice fwd_c = choice(P->cfg[SKEI_STAGE_FWD].shape, 8);
@@ -425,11 +449,7 @@ int skei_ei_plan_configure(skei_ei_plan *plan, int stage, int dispatch, int shap
 {
     if (!plan || stage < 0 || stage >= kStages) return SKEI_EINVAL;
     if (dispatch != SKEI_DISPATCH_PERSISTENT && dispatch != SKEI_DISPATCH_STATIC) return SKEI_EINVAL;
-    if (is_ray_stage(stage)) {
-        const int rpt = shape % 100, lines = shape % 10000 / 100;
-        if (shape < 0 || shape >= 40000 || rpt > 4 || !(lines == 0 || lines == 4 || lines == 8 || lines == 16))
-            return SKEI_EINVAL;
-    }
+    if (is_ray_stage(stage) && !ray_code_valid(shape)) return SKEI_EINVAL;
     if (is_gather_stage(stage) && !(shape == 0 || shape == 1 || shape == 2 || shape == 4 || shape == 14 ||
                                      shape == 24 || shape == 44))
         return SKEI_EINVAL;
@@ -454,10 +474,7 @@ int skei_ei_plan_get_config(const skei_ei_plan *plan, int stage, int *dispatch, 
     if (dispatch) *dispatch = plan->cfg[stage].dispatch;
     if (shape) {
         const StageTable &t = plan->tab[stage];
-        *shape = is_ray_stage(stage)
-                     ? t.ray.rpt + 100 * (plan->cfg[stage].shape % 10000 / 100) + (t.ray.waves == 3 ? 10000 : 0) +
-                           (plan->cfg[stage].shape >= 20000 ? 20000 : 0)
-                     : is_gather_stage(stage) ? t.ga : 0;
+        *shape = is_ray_stage(stage) ? ray_code(t.ray, plan->cfg[stage].shape) : is_gather_stage(stage) ? t.ga : 0;
     }
     return SKEI_OK;
 }
@@ -492,13 +509,18 @@ int skei_ei_plan_autotune(skei_ei_plan *plan, void *stream, int reps, const char
         }
         std::vector<int> shapes{0};
         if (is_ray_stage(s))
-            shapes = {1, 2, 3, 4, 802, 803, 402, 403, 10002, 10802, 10003, 10004, 10803, 30402, 30802, 20402, 20403};
+            shapes = {1,     2,     3,     4,     802,   803,   402,   403,   10002, 10802, 10003, 10004,
+                      10803, 30402, 30802, 20402, 20403, 40401, 40801, 40802, 80401, 80801};
         if (is_gather_stage(s)) shapes = {1, 2, 4, 14, 24, 44};
         float best_ms = 3.0e38f;
         best = plan->cfg[s];
         for (int d : {SKEI_DISPATCH_PERSISTENT, SKEI_DISPATCH_STATIC}) {
             for (int sh : shapes) {
-                if ((rc = skei_ei_plan_configure(plan, s, d, sh))) break;
+                if ((rc = skei_ei_plan_configure(plan, s, d, sh))) {
+                    if (rc != SKEI_ERANGE) break;
+                    rc = SKEI_OK;   // a shape the problems do not fit (e.g. too many rays per thread): skip it
+                    continue;
+                }
                 if ((rc = run_stage(plan, s, st))) break;   // warm-up
                 std::vector<float> ms;
                 for (int r = 0; r < reps && rc == SKEI_OK; r++) {

@@ -256,7 +256,7 @@ enum GatherKind : int { kGatherJosephAdj = 0, kGatherBackproject = 1 };
 struct RayShape {
     int rpt;
     int unroll;
-    int waves;   // per workgroup: 3 or 4
+    int waves;   // per workgroup: 3, 4, 6 or 8 (6 and 8 with at most 2 rays per thread)
     size_t shm;
 };
 
@@ -289,7 +289,7 @@ int reduce_run(const JobList<RedJob> &L, hipStream_t st);
 //   split: detector segments per angle
 struct RayTune {
     int group = 0, lines = 0, split = 0;
-    int waves = 0;   // waves per workgroup (3 or 4; 0 = whichever leaves fewer ray slots empty)
+    int waves = 0;   // waves per workgroup (3, 4, 6 or 8; 0 = 3 or 4, whichever leaves fewer ray slots empty)
     int units = 2;   // march units per LDS chunk (2 or 4)
 };
 
@@ -312,6 +312,9 @@ RampJob make_row_sumsq_job(const struct ::skei_geom *g, const float *p, long lon
 RampJob make_loss_job(const RedJob &r);
 int ramp_block(int n_det);      // threads per row
 size_t ramp_shm(int n_det);     // LDS bytes per row
+// Host walks of the LDS reads of the ramp and ray kernels (bounds self-checks).
+void ramp_lds_reads(int n_det, long long out[5]);
+void ray_lds_reads(int n, long long out[3]);
 
 RotJob make_rot_job(const float *x, int batch, int copies, int n, const float *cs, float *out, float *outT);
 RotAdjJob make_rot_adj_job(const float *h, int batch, int copies, int n, const float *cs, float alpha,

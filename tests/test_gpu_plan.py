@@ -83,8 +83,9 @@ def test_plan_bitwise_equals_single_calls_in_every_configuration(skei):
     assert_bitwise(plan, refs, "default")
     for d in (capi.DISPATCH_PERSISTENT, capi.DISPATCH_STATIC):
         # ray shapes: rays per thread, + 100 x unit lines, + 10000 for three-wave workgroups,
-        # + 20000 for four-unit LDS chunks
-        for rpt, ga in ((1, 1), (2, 2), (3, 4), (4, 1), (10802, 14), (10003, 24), (1604, 44), (30402, 2), (20803, 1)):
+        # + 20000 for four-unit LDS chunks, + 40000 / 80000 for six / eight waves
+        for rpt, ga in ((1, 1), (2, 2), (3, 4), (4, 1), (10802, 14), (10003, 24), (1604, 44), (30402, 2), (20803, 1),
+                        (40801, 1), (40402, 14), (80801, 24), (81602, 44), (60401, 2)):
             for s in capi.STAGES:
                 shape = rpt if s in ("fwd", "bp_T") else ga if s in ("bp_resid", "adj") else 0
                 plan.configure(s, d, shape)
