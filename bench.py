@@ -70,24 +70,31 @@ def parse():
     return ap.parse_args()
 
 
-def algorithmic_flops(stage, w, widths):
-    """Algorithmic floating-point work of one launch of `stage` (2 flops per
-    tap / multiply-add), from the per-unit counts of each operator."""
+def algorithmic_flops(stage, w, widths, widths_mc):
+    """Algorithmic floating-point work of one launch of `stage`: 2 flops per
+    nonzero matrix entry applied (one multiply-add), counted from the
+    operators' closed-form entries, never from what a kernel marches.
+
+    - Joseph A (and A^T): entry (a, k), p is Lambda((s_k - s_p)/w_a)/w_a, so a
+      pixel has on average 2 w_a nonzero detectors per angle: 2 w_a N^2
+      entries per listed angle.
+    - Pixel-driven B (and B^T): entry Lambda(s_p + c_D - k) has on average 2
+      nonzero detectors per (pixel, angle): 2 N^2 entries per listed angle.
+    - Ram-Lak H (symmetric form): h(0) and the odd offsets, (N_det + 1)/2
+      multiply-adds per output sample.
+    - Rotation T: 4 bilinear taps per output pixel.
+    `widths` holds w_a of the sketch's angles, `widths_mc` those of the MC angles."""
     n, nd, c, m, b = w["n"], w["n_det"], w["copies"], w["m"], w["batch"]
-    na = w["n_angles"]
     bc = b * c
-    if stage == "fwd":                 # Joseph: 2 taps per major-axis line per ray (A_S on copies + A_mc)
-        return 2.0 * (2 * n) * (bc * m + b * na) * nd
-    if stage == "adj":                 # 2 taps per (pixel, angle): A_S^T on copies + A_mc^T
-        return 2.0 * 2 * n * n * (bc * m + b * na)
-    if stage == "bp_resid":
-        return 2.0 * 2 * n * n * bc * m
-    if stage == "bp_T":                # 2/w pixels within unit distance per line, per ray
-        return 2.0 * n * nd * bc * float(np.sum(2.0 / widths))
-    if stage in ("ramp", "ramp_T"):    # symmetric form: one multiply-add per odd offset pair + centre
+    nn = float(n) * n
+    if stage in ("fwd", "adj"):        # A_S on the copies + A_mc on the image (A^T: the same entries)
+        return 2.0 * 2.0 * nn * (bc * float(np.sum(widths)) + b * float(np.sum(widths_mc)))
+    if stage in ("bp_resid", "bp_T"):  # B_S or B_S^T on the copies
+        return 2.0 * 2.0 * nn * bc * m
+    if stage in ("ramp", "ramp_T"):
         return 2.0 * bc * m * nd * (nd + 1) / 2
     if stage in ("rotate", "rotate_adj"):
-        return 2.0 * 4 * n * n * bc
+        return 2.0 * 4 * nn * bc
     return 0.0
 
 
@@ -179,6 +186,8 @@ def main():
     cs = torch.from_numpy(synth.cos_sin(synth.rotation_angles(c)).astype(np.float32)).to(dev)
     sketch = geom.sketch(idx)
     widths = np.maximum(np.abs(np.cos(math.pi * idx / na)), np.abs(np.sin(math.pi * idx / na)))
+    all_a = np.arange(na)
+    widths_mc = np.maximum(np.abs(np.cos(math.pi * all_a / na)), np.abs(np.sin(math.pi * all_a / na)))
 
     # the product path: a one-problem EI plan, autotuned (cached per shape)
     plan = ei.EIPlan([ei.EIProblem(geom, x0, y, sketch, cs, lam)])
@@ -201,16 +210,14 @@ def main():
 
     rays_per_step = 2.0 * (na + c * m) * nd * b
     value = rays_per_step / (ms_per_step * 1e-3) / 1e9
-    flops = algorithmic_flops(dominant, w, widths)
+    flops = algorithmic_flops(dominant, w, widths, widths_mc)
     achieved = flops / (dom_ms * 1e-3) / 1e12
     traffic, l2_hit = traffic_for(dominant, tuned[dominant][1])
     roofline = {
         "bound": "alu", "kernel": dominant, "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
         "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
         "frac_nonpacked": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4),
-        "launch_ms": round(dom_ms, 5), "traffic": traffic, "l2_hit_rate": l2_hit,
-        "gather_equiv_hbm_frac": round(gather_equiv_bytes(dominant, w, widths) / (dom_ms * 1e-3) / 1e9
-                                       / PEAK_HBM_GBS, 4),
+        "launch_ms": round(dom_ms, 5), "flops_per_launch": flops, "traffic": traffic, "l2_hit_rate": l2_hit,
     }
     fwd_adj_ms = stage_ms["fwd"] + stage_ms["adj"]
     out = {
@@ -226,8 +233,14 @@ def main():
         "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
         "tuned": {k: list(v) for k, v in tuned.items()},
         "roofline": roofline,
+        # informational, not a roofline: the bytes the stage would move if every
+        # tap were an HBM read (4 B per nonzero entry) over the launch time; it
+        # exceeds 1 whenever the on-chip caches serve the taps
+        "gather_equiv_hbm_rate_informational": round(
+            gather_equiv_bytes(dominant, w, widths, widths_mc) / (dom_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
     }
     plan.close()
+    out["plain_ops"] = plain_ops_leg()
     if not args.no_batched:
         out["batched"] = batched_leg(args)
     if not args.no_serving:
@@ -237,10 +250,65 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def gather_equiv_bytes(stage, w, widths):
-    """4 bytes per tap read plus 4 per output written: the bytes the stage
-    would move if every tap came from HBM (the gather-equivalent traffic)."""
-    return 2.0 * algorithmic_flops(stage, w, widths)   # 2 flops per tap -> 4 B per tap; outputs are negligible
+def gather_equiv_bytes(stage, w, widths, widths_mc):
+    """4 bytes per nonzero entry applied: the bytes the stage would move if
+    every tap came from HBM (outputs are negligible beside them)."""
+    return 2.0 * algorithmic_flops(stage, w, widths, widths_mc)   # 2 flops per entry -> 4 B per entry
+
+
+def plain_ops_leg():
+    """The plain-operator workload: one 64 x 64 ellipse phantom, 60 angles,
+    91 detectors, batch 1; radon_fwd, radon_adj and Ram-Lak fbp with the
+    full scan and with every 4th angle (m = 15).  Each call is timed with
+    HIP events over 200 back-to-back launches (launch-latency bound at this
+    size); GRays/s = m N_det / (t_fwd + t_adj).  A parity sample compares
+    every output with the FP64 oracle on the same float inputs."""
+    import torch
+
+    import oracle
+    from paper_2411_05771_amd import capi, ops, synth
+    n, na, nd = 64, 60, 91
+    dev = torch.device("cuda", 0)
+    geom = ops.Geometry(n, na, nd)
+    xh = synth.ellipse_phantom(n, synth.SEED_PHANTOM).astype(np.float64)
+    x = torch.from_numpy(xh.astype(np.float32)).to(dev)[None].contiguous()
+    stream = torch.cuda.current_stream()
+    out = {"workload": "plain_ops_64sq_60ang_91det_batch1"}
+
+    def time_us(fn, reps=200):
+        for _ in range(10):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / reps
+
+    def rel(got, want):
+        return float(np.max(np.abs(got.cpu().numpy().astype(np.float64) - want)) / np.max(np.abs(want)))
+
+    for name, idx in (("full", np.arange(na, dtype=np.int32)), ("every4", synth.interleaved_sketch(na, 4, 0))):
+        sk = geom.sketch(idx)
+        m = idx.size
+        y = ops.radon_fwd_(geom, x, sk)
+        xa = ops.radon_adj_(geom, y, sk)
+        xf = ops.fbp_(geom, y, sk)
+        yb, xab, xfb = torch.empty_like(y), torch.empty_like(xa), torch.empty_like(xf)
+        t_f = time_us(lambda: ops.radon_fwd_(geom, x, sk, out=yb))
+        t_a = time_us(lambda: ops.radon_adj_(geom, y, sk, out=xab))
+        work = torch.empty(max(1, int(capi.query("skei_fbp_workspace_bytes", geom.handle, 1, m))),
+                           dtype=torch.uint8, device=dev)
+        t_fbp = time_us(lambda: ops.fbp_(geom, y, sk, out=xfb, work=work))
+        yh = y.cpu().numpy().astype(np.float64)
+        par = {"radon_fwd": rel(y, oracle.radon_fwd(xh[None], na, nd, idx)),
+               "radon_adj": rel(xa, oracle.radon_adj(yh, n, na, idx)),
+               "fbp": rel(xf, oracle.fbp(yh, n, na, idx))}
+        out[name] = {"m": int(m), "fwd_us": round(t_f, 3), "adj_us": round(t_a, 3), "fbp_us": round(t_fbp, 3),
+                     "fwd_adj_grays": round(m * nd / ((t_f + t_a) * 1e-6) / 1e9, 4),
+                     "parity_relerr": {k: float(f"{v:.3e}") for k, v in par.items()}}
+    return out
 
 
 def batched_leg(args):
@@ -333,6 +401,18 @@ def source_sha():
     return h.hexdigest()[:16]
 
 
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, idx, target_s, rays_per_step):
     """The FP64 oracle (as it stands) timed on whole EI steps of the workload,
     repeated until about `target_s` seconds of work; its inputs are made by
@@ -357,7 +437,8 @@ def cpu_baseline(w, idx, target_s, rays_per_step):
     per_step = t_total / reps
     base = {"value": round(rays_per_step / per_step / 1e9, 6), "unit": "GRays/s", "cores": oracle.num_threads(),
             "kind": "oracle", "sample": f"{reps} full EI steps of the same workload (float64, OpenMP)",
-            "s_per_step": round(per_step, 4)}
+            "s_per_step": round(per_step, 4), "cpu_model": cpu_model(), "host_cpus_visible": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0))}
     dev = torch.device("cuda", 0)
     geom = ops.Geometry(n, na, nd)
     step = ei.EIStep(geom, torch.from_numpy(y.astype(np.float32)).to(dev), geom.sketch(idx),
