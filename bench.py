@@ -13,11 +13,12 @@ value = projector rays per step / step time, in GRays/s: a step evaluates
 the full-scan A and the sketched A_S on every copy once forward and once
 adjoint, i.e. 2 * (N_theta + C*m) * N_det rays.
 
-Extra legs (same JSON line): "batched" -- 64 uneven problems in one plan vs
-one call per problem; "serving" -- Poisson-arriving adaptation jobs under an
-HBM budget, continuous batching vs per-call, p50/p99 latency; "cpu_baseline"
-and "parity" -- the FP64 oracle timed on the host and compared with the
-device on oracle-made inputs.
+Extra legs (same JSON line): "plain_ops" -- the 64 x 64 plain operators;
+"batched" -- 64 uneven problems in one plan vs one call per problem;
+"serving" -- Poisson-arriving adaptation jobs under an HBM budget at a sweep
+of arrival rates, continuous batching vs per-call, p50/p99 latency and
+GRays/s; "cpu_baseline" and "parity" -- the FP64 oracle timed on the host
+and compared with the device on oracle-made inputs.
 
 Prints ONE JSON line.  --gpus N > 1 is refused: the path runs on one GPU.
 """
@@ -62,8 +63,11 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the uneven 64-problem leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-jobs", type=int, default=12)
-    ap.add_argument("--serve-rate", type=float, default=1.5, help="Poisson arrival rate, jobs per second")
-    ap.add_argument("--budget-gb", type=float, default=4.0, help="HBM budget of the serving leg")
+    ap.add_argument("--serve-rates", default="1,2,3,4,8", help="Poisson arrival rates swept, jobs per second")
+    ap.add_argument("--serve-jobs-small", type=int, default=24)
+    ap.add_argument("--serve-rates-small", default="10,20,40,80,160",
+                    help="arrival rates of the small-job sweep, jobs per second")
+    ap.add_argument("--budget-gb", type=float, default=1.0, help="HBM budget of the serving leg")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (text); default: a scratch copy of the package's MI355X defaults")
     ap.add_argument("--tune-reps", type=int, default=5, help="timed launches per autotuner candidate")
@@ -350,28 +354,63 @@ def batched_leg(args):
                                                                                         "per_problem": 8 * len(specs)}}
 
 
+def serving_sweep(specs_at, rates, budget, executors, label):
+    """Runs the same seeded jobs at each arrival rate with each executor."""
+    from paper_2411_05771_amd import serve
+    specs0 = specs_at(rates[0])
+    rays = sum(serve.job_rays(s) for s in specs0)
+    out = {"rays_per_point": rays, "points": []}
+    host_y = None
+    for rate in rates:
+        specs = specs_at(rate)
+        point = {"rate": rate}
+        for name, kw in executors:
+            ex = serve.GpuExecutor(**kw)
+            if host_y is None:
+                ex.prepare(specs)
+                host_y = dict(ex.host_y)
+            else:
+                ex.host_y.update(host_y)
+            rep = serve.Server(ex, budget).run(specs)
+            builds = ex.plan_builds
+            ex.close()
+            point[name] = {"p50_s": round(rep.percentile(50), 4), "p99_s": round(rep.percentile(99), 4),
+                           "makespan_s": round(rep.makespan, 3), "grays": round(rays / rep.makespan / 1e9, 4),
+                           "done": len(rep.done), "rejected": len(rep.rejected), "steps": rep.iterations,
+                           "max_batch": max(rep.batch_sizes) if rep.batch_sizes else 0,
+                           "peak_gb": round(rep.peak_bytes / (1 << 30), 3), "plan_builds": builds}
+            print(f"[serving {label}] rate {rate} {name}: {point[name]}", file=sys.stderr, flush=True)
+        out["points"].append(point)
+    return out
+
+
 def serving_leg(args):
-    """Poisson-arriving test-time adaptation jobs (N in {256, 512, 1024},
-    N_theta ~ U{180..1440}, ratio in {2, 4, 8}, 16 copies, 50 iterations)
-    under an HBM budget: continuous batching vs per-call launches on the
-    same arrivals."""
-    from paper_2411_05771_amd import serve, synth
-    specs = synth.poisson_jobs(args.serve_jobs, rate=args.serve_rate)
+    """Poisson-arriving test-time adaptation jobs (16 copies, 50 iterations
+    each) under an HBM budget, at a sweep of arrival rates (the same seeded
+    jobs, arrival gaps scaled by the rate): continuous batching vs per-call
+    launches.
+      mixed: N in {256, 512, 1024}, N_theta ~ U{180..1440}, ratio in {2, 4, 8};
+      small: N = 256, N_theta ~ U{180..360}, ratio in {2, 4, 8}.
+    Executors: "per_call" (one plan per job, one iteration of every job per
+    step), "batched" (jobs of one geometry size and repetition count share a
+    plan; cheap jobs take up to 1/4 of the costliest job's iteration per
+    step) and "batched_share1" (every cost class about the same device time
+    per step)."""
+    from paper_2411_05771_amd import synth
     budget = int(args.budget_gb * (1 << 30))
-    res = {"workload": f"poisson_{args.serve_jobs}_jobs_rate{args.serve_rate}", "budget_gb": args.budget_gb,
-           "jobs": args.serve_jobs, "rate_jobs_per_s": args.serve_rate}
-    rays = sum(serve.job_rays(s) for s in specs)
-    for name, batched in (("batched", True), ("per_call", False)):
-        ex = serve.GpuExecutor(batched=batched)
-        ex.prepare(specs)
-        rep = serve.Server(ex, budget).run(specs)
-        ex.close()
-        res[name] = {"p50_s": round(rep.percentile(50), 4), "p99_s": round(rep.percentile(99), 4),
-                     "makespan_s": round(rep.makespan, 3), "grays": round(rays / rep.makespan / 1e9, 4),
-                     "done": len(rep.done), "rejected": len(rep.rejected), "iterations": rep.iterations,
-                     "max_batch": max(rep.batch_sizes) if rep.batch_sizes else 0,
-                     "peak_gb": round(rep.peak_bytes / (1 << 30), 3)}
-        print(f"[serving] {name}: {res[name]}", file=sys.stderr, flush=True)
+    executors = (("per_call", dict(batched=False)), ("batched", dict(batched=True)),
+                 ("batched_share1", dict(batched=True, share=1.0)))
+    res = {"budget_gb": args.budget_gb, "executors": [e[0] for e in executors]}
+    rates = [float(r) for r in args.serve_rates.split(",")]
+    res["mixed"] = dict(workload=f"poisson_{args.serve_jobs}_jobs_256_to_1024sq_180_to_1440ang_50_iters",
+                        jobs=args.serve_jobs, rates_jobs_per_s=rates,
+                        **serving_sweep(lambda r: synth.poisson_jobs(args.serve_jobs, rate=r), rates, budget,
+                                        executors, "mixed"))
+    rates_s = [float(r) for r in args.serve_rates_small.split(",")]
+    small = lambda r: synth.poisson_jobs(args.serve_jobs_small, rate=r, sizes=(256,), angles=(180, 360))
+    res["small"] = dict(workload=f"poisson_{args.serve_jobs_small}_jobs_256sq_180_to_360ang_50_iters",
+                        jobs=args.serve_jobs_small, rates_jobs_per_s=rates_s,
+                        **serving_sweep(small, rates_s, budget, executors, "small"))
     return res
 
 

@@ -153,20 +153,36 @@ def iteration_cost(spec) -> float:
     return float((spec["n_angles"] + spec["copies"] * spec["m"]) * spec["n_det"] * spec["n"])
 
 
+def executor_share(batched: bool, fair: bool | None = None, share: float | None = None) -> float:
+    """The per-step share of GpuExecutor (see there): `share` if given, else
+    1 / 0 for fair=True / False, else 0.25 batched and 0 per call."""
+    if share is None:
+        share = (0.25 if batched else 0.0) if fair is None else (1.0 if fair else 0.0)
+    if not share >= 0.0:
+        raise ValueError("share must be >= 0")
+    return float(share)
+
+
 class GpuExecutor:
     """Runs jobs on the device through the library.
 
     batched=True : the admitted jobs run as batched EI plans -- one launch per
-                   stage for a whole class of jobs.  With fair=True (default)
-                   jobs are classed by iteration cost and each step gives every
-                   class about the same device time: a job whose iteration
-                   costs 1/k of the most expensive one's runs k iterations
-                   (capped by what it has left), so short jobs are not paced
-                   by long ones.  fair=False runs one iteration of every job
-                   per step in a single plan.
+                   stage for a whole class of jobs.
     batched=False: the per-call baseline -- each job has its own one-problem
-                   plan and the jobs' iterations run one after another, one per
-                   job per step.
+                   plan and the jobs' iterations run one after another.
+    share        : device time a cheap job may take per step, as a fraction of
+                   one iteration of the costliest active job.  A job whose
+                   iteration costs c runs max(1, floor(share * c_max / c))
+                   iterations in the step (capped by what it has left), so
+                   cheap jobs are not paced by expensive ones; jobs with equal
+                   repetitions and image and detector sizes form one class
+                   (one plan, whose launches share one shape).  share = 0 runs one
+                   iteration of every job per step (round robin, one plan when
+                   batched); share = 1 gives every cost class about the same
+                   device time per step.  Larger shares finish cheap jobs
+                   sooner (lower median latency) and slow the costliest ones
+                   (higher tail latency).  Default: 0.25 batched, 0 per call.
+                   `fair` is the older switch: True = share 1, False = share 0.
     Each job owns its scratch (allocated at admission and counted in its
     footprint), so rebuilding a plan allocates only its small work table.
     Inputs (the measured sinograms) are made once by ``prepare`` and kept in
@@ -175,19 +191,20 @@ class GpuExecutor:
     """
 
     def __init__(self, batched: bool = True, fair: bool | None = None, lam: float = 1.0,
-                 record_loss: bool = False):
+                 record_loss: bool = False, share: float | None = None):
         import torch
 
         from . import ops
         self.torch, self.ops = torch, ops
         self.dev = torch.device("cuda", torch.cuda.current_device())
         self.batched = batched
-        self.fair = batched if fair is None else bool(fair)
+        self.share = executor_share(batched, fair, share)
         self.lam = float(lam)
         self.record_loss = record_loss
         self.geoms = {}
         self.host_y = {}
-        self._plans = {}
+        self._plans = {}                  # member tokens -> plan, least recently used first
+        self.max_plans = 64
         self._tokens = itertools.count()
         self.plan_builds = 0
 
@@ -259,11 +276,11 @@ class GpuExecutor:
         only ever bound to the problems of exactly these jobs)."""
         from . import ei
         key = tuple(st.token for st in members)
-        plan = self._plans.get(key)
+        plan = self._plans.pop(key, None)
         if plan is None:
             plan = ei.EIPlan([st.problem for st in members])
-            self._plans[key] = plan
             self.plan_builds += 1
+        self._plans[key] = plan           # most recently used last
         return key, plan
 
     def _run(self, members, reps):
@@ -280,26 +297,34 @@ class GpuExecutor:
 
     def step(self, states):
         """Runs the step; returns the iterations each job advanced."""
-        if self.fair:
+        if self.share > 0:
             cmax = max(st.cost for st in states)
-            reps = [max(1, min(int(cmax // st.cost), st.spec["iters"] - st.it)) for st in states]
+            reps = [max(1, min(int(self.share * cmax // st.cost), st.spec["iters"] - st.it)) for st in states]
         else:
             reps = [1] * len(states)
         if any(st.it + r > st.spec["iters"] for st, r in zip(states, reps)):
             raise RuntimeError("a job was stepped past its iterations")
-        used = set()
         if self.batched:
+            # a class shares every launch of a plan, and a launch takes one
+            # shape for all its jobs (rays per thread from the widest detector
+            # row, ...): only jobs of one geometry size share a class
             classes = {}
             for st, r in zip(states, reps):
-                classes.setdefault(r, []).append(st)
-            for r in sorted(classes, reverse=True):
-                used.add(self._run(classes[r], r))
+                classes.setdefault((r, st.spec["n"], st.spec["n_det"]), []).append(st)
+            for key in sorted(classes, reverse=True):
+                self._run(classes[key], key[0])
         else:
             for st, r in zip(states, reps):
-                used.add(self._run([st], r))
-        # plans of classes that no longer exist free their tables
-        for key in [k for k in self._plans if k not in used]:
+                self._run([st], r)
+        # A class plan stays cached while all its members are active (class
+        # membership changes as repetition counts shift, and recurs); plans
+        # with a member that has left, and the least recently used beyond
+        # the cache size, free their tables.
+        active = {st.token for st in states}
+        for key in [k for k in self._plans if not active.issuperset(k)]:
             self._plans.pop(key).close()
+        while len(self._plans) > self.max_plans:
+            self._plans.pop(next(iter(self._plans))).close()
         self.torch.cuda.synchronize()
         return reps
 

@@ -187,7 +187,7 @@ class _FakePlan:
         self.closed = True
 
 
-def _host_executor(monkeypatch, batched=True, fair=False):
+def _host_executor(monkeypatch, batched=True, share=0.0):
     """A GpuExecutor whose device parts (torch sync, plans, per-iteration
     input copies) are replaced by host fakes; step() and the plan cache are
     the real ones."""
@@ -197,18 +197,18 @@ def _host_executor(monkeypatch, batched=True, fair=False):
     from paper_2411_05771_amd import ei
     monkeypatch.setattr(ei, "EIPlan", _FakePlan)
     ex = object.__new__(serve.GpuExecutor)
-    ex.batched, ex.fair, ex.record_loss = batched, fair, False
-    ex._plans, ex._tokens, ex.plan_builds = {}, itertools.count(), 0
+    ex.batched, ex.share, ex.record_loss = batched, share, False
+    ex._plans, ex._tokens, ex.plan_builds, ex.max_plans = {}, itertools.count(), 0, 64
     ex.torch = types.SimpleNamespace(cuda=types.SimpleNamespace(synchronize=lambda: None))
     ex._inputs = lambda st: None
     return ex
 
 
-def _state(ex, iters=1, cost=1.0):
+def _state(ex, iters=1, cost=1.0, n=64, n_det=91):
     st = serve._JobState()
     st.token = next(ex._tokens)          # as GpuExecutor.start draws it
     st.problem = object()
-    st.spec = {"iters": iters}
+    st.spec = {"iters": iters, "n": n, "n_det": n_det}
     st.it = 0
     st.cost = cost
     return st
@@ -238,10 +238,67 @@ def test_plan_cache_never_serves_a_finished_jobs_plan(monkeypatch):
 
 
 def test_per_call_executor_honours_fair_repetitions(monkeypatch):
-    """batched=False with fair=True: each job runs as many iterations as the
+    """batched=False with share 1: each job runs as many iterations as the
     step reports for it."""
-    ex = _host_executor(monkeypatch, batched=False, fair=True)
+    ex = _host_executor(monkeypatch, batched=False, share=1.0)
     cheap, dear = _state(ex, iters=10, cost=1.0), _state(ex, iters=10, cost=4.0)
     reps = ex.step([cheap, dear])
     assert reps == [4, 1]
     assert cheap.it == 4 and dear.it == 1
+
+
+@pytest.mark.parametrize("share,want", [(0.0, [1, 1, 1]), (0.25, [2, 1, 1]), (0.5, [4, 2, 1]), (1.0, [8, 4, 1])])
+def test_share_sets_the_repetitions_of_cheap_jobs(monkeypatch, share, want):
+    """A job of iteration cost c runs max(1, floor(share * c_max / c))
+    iterations per step, capped by what it has left; equal repetitions form
+    one class (one plan run per repetition)."""
+    ex = _host_executor(monkeypatch, batched=True, share=share)
+    sts = [_state(ex, iters=10, cost=1.0), _state(ex, iters=10, cost=2.0), _state(ex, iters=10, cost=8.0)]
+    assert ex.step(sts) == want
+    assert [st.it for st in sts] == want
+    runs = sorted(len(plan.runs) for plan in ex._plans.values())
+    assert sum(runs) == sum(sorted(set(want)))
+    left = _state(ex, iters=1, cost=1.0)              # capped by what it has left
+    assert ex.step([left, _state(ex, iters=10, cost=8.0)])[0] == 1
+
+
+def test_executor_share_defaults():
+    assert serve.executor_share(True) == 0.25
+    assert serve.executor_share(False) == 0.0
+    assert serve.executor_share(True, fair=True) == 1.0
+    assert serve.executor_share(True, fair=False) == 0.0
+    assert serve.executor_share(False, share=0.5) == 0.5
+    with pytest.raises(ValueError):
+        serve.executor_share(True, share=-1.0)
+
+
+def test_class_plans_are_kept_while_their_members_run(monkeypatch):
+    """Repetition classes regroup as jobs near their end; a class plan is kept
+    while all its members are active (no rebuild when the class recurs) and
+    closed once a member has left; the cache holds at most max_plans plans."""
+    ex = _host_executor(monkeypatch, batched=True, share=1.0)
+    a, b = _state(ex, iters=3, cost=1.0), _state(ex, iters=10, cost=2.0)
+    assert ex.step([a, b]) == [2, 1]          # classes (a,) x2 and (b,) x1
+    assert ex.step([a, b]) == [1, 1]          # a has one left: class (a, b)
+    assert ex.plan_builds == 3
+    kept = dict(ex._plans)
+    assert set(kept) == {(a.token,), (b.token,), (a.token, b.token)}
+    ex.step([b])                              # a has finished
+    assert ex.plan_builds == 3                # (b,) served from the cache
+    assert all(p.closed for k, p in kept.items() if a.token in k)
+    assert list(ex._plans) == [(b.token,)]
+    ex.max_plans = 1
+    c = _state(ex, iters=10, cost=2.0)
+    ex.step([b, c])
+    assert len(ex._plans) == 1
+
+
+def test_classes_hold_one_geometry_size(monkeypatch):
+    """Jobs of different image or detector sizes never share a plan (its
+    launches take one shape); equal sizes and repetitions do."""
+    ex = _host_executor(monkeypatch, batched=True, share=0.0)
+    a, b = _state(ex, iters=5, n=64, n_det=91), _state(ex, iters=5, n=64, n_det=91)
+    c = _state(ex, iters=5, n=128, n_det=182)
+    ex.step([a, b, c])
+    assert sorted(len(k) for k in ex._plans) == [1, 2]
+    assert (c.token,) in ex._plans and (a.token, b.token) in ex._plans
