@@ -137,17 +137,14 @@ int ei_problem_jobs(const skei_ei_problem &p, const EiBuffers &b, const RayChoic
     J.rot[0] = make_rot_job(p.x, batch, copies, n, p.cos_sin, b.z, b.zT);
     J.rot[1] = make_rot_job(p.x, batch, 1, n, nullptr, nullptr, b.xT);
     RayTune tf = g->tune_fwd, tb = g->tune_bpt;
-    // built-in march units when the geometry is not tuned: 8 lines (forward)
-    // and 4 lines (B^T), four units per LDS chunk for images up to 512 (the
-    // autotuner's MI355X choice at 256 x 256), two above (occupancy)
-    const int units = n <= 512 ? 4 : 2;
-    if (tf.lines == 0) {
-        tf.lines = 8;
-        tf.units = units;
-    }
+    // built-in march units when the geometry is not tuned (the autotuner's
+    // MI355X choices at 256 x 256): 8 lines, two units per LDS chunk for the
+    // forward; 4 lines, four units per chunk for B^T up to 512 (8 lines and
+    // two units above, for occupancy)
+    if (tf.lines == 0) tf.lines = 8;
     if (tb.lines == 0) {
         tb.lines = n <= 512 ? 4 : 8;
-        tb.units = units;
+        tb.units = n <= 512 ? 4 : 2;
     }
     if (!fwd.own) {
         tf = RayTune{};
