@@ -245,6 +245,7 @@ def main():
     }
     plan.close()
     out["plain_ops"] = plain_ops_leg()
+    out["paper_shaped"] = paper_shaped_leg()
     if not args.no_batched:
         out["batched"] = batched_leg(args)
     if not args.no_serving:
@@ -312,6 +313,79 @@ def plain_ops_leg():
         out[name] = {"m": int(m), "fwd_us": round(t_f, 3), "adj_us": round(t_a, 3), "fbp_us": round(t_fbp, 3),
                      "fwd_adj_grays": round(m * nd / ((t_f + t_a) * 1e-6) / 1e9, 4),
                      "parity_relerr": {k: float(f"{v:.3e}") for k, v in par.items()}}
+    return out
+
+
+def paper_shaped_leg():
+    """The paper's CT geometry (Sec. 4.1.1 and 4.2.1): a 512 x 512 ellipse
+    phantom, 100 uniformly spaced angles, 726 detectors, interleaved sketches
+    S_k = {k, k+N, k+2N, ...} with N in {1, 2, 5, 10, 20} (all, 50, 20, 10
+    and 5 % of the angles).  Per N: the sketched operators' times (HIP events
+    over 50 back-to-back calls), the one-call EI step with 16 rotated copies
+    and the sketched MC term S y - A_S x of Algorithm 2, and the Theorem 1
+    series with the network taken as the identity:
+        full   = mean_c ||v_c - fbp(A v_c)||,
+        sketch = mean_c mean_k ||v_c - fbp_{S_k}(A_{S_k} v_c)||  (k = 0..N-1),
+    v_c = T_c fbp(y) for 4 seeded rotations; the theorem places `sketch`
+    within r delta of `full` (r = max ||v_c||) with a delta the paper does not
+    give, so the series is informational (the tests check its values against
+    the oracle)."""
+    import torch
+
+    from paper_2411_05771_amd import ei, ops, synth
+    n, na, nd = 512, 100, 726
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream()
+    geom = ops.Geometry(n, na, nd)
+    w = dict(n=n, batch=1)
+    x0, y = ei_inputs(geom, w, dev)
+    cs = torch.from_numpy(synth.cos_sin(synth.rotation_angles(16)).astype(np.float32)).to(dev)
+    v = ops.rotate_(x0, torch.from_numpy(synth.cos_sin(synth.rotation_angles(4, synth.SEED_ROTATION + 1))
+                                         .astype(np.float32)).to(dev)).reshape(4, n, n).contiguous()
+
+    def time_us(fn, reps=50):
+        for _ in range(5):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / reps
+
+    def resid(sk):
+        r = v - ops.fbp_(geom, ops.radon_fwd_(geom, v, sk), sk)
+        return torch.linalg.vector_norm(r.double().reshape(4, -1), dim=1)
+
+    full = resid(geom.full())
+    vnorm = torch.linalg.vector_norm(v.double().reshape(4, -1), dim=1)
+    out = {"workload": "paper_ct_512sq_100ang_726det", "splits": []}
+    for split in (1, 2, 5, 10, 20):
+        sk = geom.sketch(synth.interleaved_sketch(na, split, 0))
+        xb = torch.empty_like(x0)
+        yb = torch.empty((1, sk.m, nd), device=dev)
+        work = torch.empty(max(1, int(ops.capi.query("skei_fbp_workspace_bytes", geom.handle, 1, sk.m))),
+                           dtype=torch.uint8, device=dev)
+        ys = ops.radon_fwd_(geom, x0, sk)
+        t_f = time_us(lambda: ops.radon_fwd_(geom, x0, sk, out=yb))
+        t_a = time_us(lambda: ops.radon_adj_(geom, ys, sk, out=xb))
+        t_fbp = time_us(lambda: ops.fbp_(geom, ys, sk, out=xb, work=work))
+        step = ei.EIStep(geom, y, sk, cs, 1.0, mc=sk)
+        grad = torch.empty_like(x0)
+        t_ei = time_us(lambda: step(x0, grad), reps=20)
+        sk_res = torch.stack([resid(geom.sketch(synth.interleaved_sketch(na, split, k))) for k in range(split)])
+        out["splits"].append({
+            "N": split, "m": sk.m, "fraction": round(sk.m / na, 3), "fwd_us": round(t_f, 2), "adj_us": round(t_a, 2),
+            "fbp_us": round(t_fbp, 2), "ei_step_us": round(t_ei, 2),
+            "theorem1_full": round(float(full.mean()), 6), "theorem1_sketch": round(float(sk_res.mean()), 6),
+            "theorem1_gap_over_r": round(float((sk_res.mean() - full.mean()) / vnorm.max()), 6)})
+    base = out["splits"][0]
+    for e in out["splits"]:
+        e["ei_step_speedup_vs_full"] = round(base["ei_step_us"] / e["ei_step_us"], 3)
+    out["paper_ttt_speedup_context"] = {"hardware": "RTX 4060 Ti, whole TTT epoch incl. U-Net",
+                                        "fraction_0.5": 3.59, "fraction_0.2": 7.13, "fraction_0.1": 7.65,
+                                        "fraction_0.05": 8.10}
     return out
 
 
