@@ -62,6 +62,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-batched", action="store_true", help="skip the uneven 64-problem leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-ttt", action="store_true", help="skip the test-time-training leg")
     ap.add_argument("--serve-jobs", type=int, default=12)
     ap.add_argument("--serve-rates", default="1,2,3,4,8", help="Poisson arrival rates swept, jobs per second")
     ap.add_argument("--serve-jobs-small", type=int, default=24)
@@ -246,6 +247,8 @@ def main():
     plan.close()
     out["plain_ops"] = plain_ops_leg()
     out["paper_shaped"] = paper_shaped_leg()
+    if not args.no_ttt:
+        out["ttt"] = ttt_leg()
     if not args.no_batched:
         out["batched"] = batched_leg(args)
     if not args.no_serving:
@@ -386,6 +389,71 @@ def paper_shaped_leg():
     out["paper_ttt_speedup_context"] = {"hardware": "RTX 4060 Ti, whole TTT epoch incl. U-Net",
                                         "fraction_0.5": 3.59, "fraction_0.2": 7.13, "fraction_0.1": 7.65,
                                         "fraction_0.05": 8.10}
+    return out
+
+
+def ttt_leg():
+    """Sketched equivariant test-time training (Algorithm 2) on the paper's CT
+    geometry (512 x 512, 100 angles, 726 detectors): a residual BN U-Net
+    (widths 32-256, seeded random weights: the pretrained CT100 model is not
+    available), Adam at 5e-4, one interleaved sketch S_k and one whole-degree
+    rotation per iteration.  Wall time per iteration (device-synchronised,
+    10 iterations after 3 warm-up) for every split N and for adapting all
+    parameters ("full") or only the BatchNorm affine ones ("bn"); and the CT
+    operators' share: the same loss and backward with the network taken as
+    the identity."""
+    import copy
+
+    import torch
+
+    from paper_2411_05771_amd import ops, synth, ttt
+    n, na, nd = 512, 100, 726
+    dev = torch.device("cuda", 0)
+    geom = ops.Geometry(n, na, nd)
+    _, y = ei_inputs(geom, dict(n=n, batch=1), dev)
+    torch.manual_seed(0)
+    base = ttt.ResUNet(width=32, depth=4).to(dev)
+    out = {"workload": "skei_ttt_512sq_100ang_726det_resunet32", **ttt.network_size(base), "modes": {}}
+
+    class _Identity(torch.nn.Module):
+        def forward(self, v):
+            return v
+
+    # the CT operators of one iteration alone: the loss and its backward with
+    # the network taken as the identity (the part the library computes)
+    x_in = ops.fbp_(geom, y, geom.full()).contiguous()
+    rot = ttt.rotation_table(dev)
+    ops_rows = []
+    for split in (1, 2, 5, 10, 20):
+        sk = geom.sketch(synth.interleaved_sketch(na, split, 0))
+        x = x_in.clone().requires_grad_(True)
+
+        def one():
+            x.grad = None
+            loss, _, _ = ttt.skei_ttt_loss(_Identity(), x, y, geom, sk, rot[36:37])
+            loss.backward()
+        for _ in range(3):
+            one()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            one()
+        torch.cuda.synchronize()
+        ops_rows.append({"N": split, "ms_per_iteration": round((time.perf_counter() - t0) / 20 * 1e3, 3)})
+    out["operators_only"] = ops_rows
+    for mode in ("full", "bn"):
+        rows = []
+        for split in (1, 2, 5, 10, 20):
+            loop = ttt.SkEITTT(copy.deepcopy(base), geom, y, splits=split, mode=mode)
+            ms = 1e3 * ttt.time_per_iteration(loop, 10, warmup=3)
+            rows.append({"N": split, "fraction": round(1.0 / split, 3), "ms_per_iteration": round(ms, 3),
+                         "last_loss": float(loop.losses[-1])})
+        for r in rows:
+            r["speedup_vs_full"] = round(rows[0]["ms_per_iteration"] / r["ms_per_iteration"], 3)
+        out["modes"][mode] = rows
+    out["paper_context"] = {"hardware": "RTX 4060 Ti", "time_per_epoch_s_full_ei": 9.56,
+                            "time_per_epoch_s_skei_50_20_10_5pct": [2.66, 1.34, 1.25, 1.18],
+                            "bn_only_full_ei": 5.45, "bn_only_skei_50_20_10_5pct": [1.46, 1.09, 1.00, 0.95]}
     return out
 
 

@@ -5,7 +5,7 @@ Submodules load lazily so that importing the seeded input generators
 """
 import importlib
 
-__all__ = ["synth", "capi", "ops", "ei", "batched", "serve", "build"]
+__all__ = ["synth", "capi", "ops", "ei", "batched", "serve", "build", "ttt"]
 
 
 def __getattr__(name):
