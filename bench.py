@@ -247,6 +247,7 @@ def main():
     plan.close()
     out["plain_ops"] = plain_ops_leg()
     out["paper_shaped"] = paper_shaped_leg()
+    out["dense_sketch"] = dense_sketch_leg()
     if not args.no_ttt:
         out["ttt"] = ttt_leg()
     if not args.no_batched:
@@ -454,6 +455,63 @@ def ttt_leg():
     out["paper_context"] = {"hardware": "RTX 4060 Ti", "time_per_epoch_s_full_ei": 9.56,
                             "time_per_epoch_s_skei_50_20_10_5pct": [2.66, 1.34, 1.25, 1.18],
                             "bn_only_full_ei": 5.45, "bn_only_skei_50_20_10_5pct": [1.46, 1.09, 1.00, 0.95]}
+    return out
+
+
+def dense_sketch_leg():
+    """Dense measurement-space sketches S = G (x) I (Gaussian G, Sec. 2.3) on
+    the matrix cores: skei_sketch_rows / _T timed with HIP events over 100
+    calls at the EI-step shape (90 x 360 mixes of 363-detector rows, 16
+    images) and at a 1024^2 / 1440-angle job's shape (180 x 1440, 1449
+    detectors, 16 images), against the FP32 matrix peak (157.3 TFLOP/s) and
+    the 8 TB/s HBM peak; and the MC residual of one 256^2 image with a dense
+    sketch, S (y - A x) (every angle projected, then mixed), against the
+    angle-subsampled S y - A_S x of the same size m."""
+    import torch
+
+    from paper_2411_05771_amd import ops, synth
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream()
+
+    def time_us(fn, reps=100):
+        for _ in range(5):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / reps
+
+    out = {"gemm": []}
+    for m, k, L, b in ((90, 360, 363, 16), (180, 1440, 1449, 16)):
+        G = torch.from_numpy(synth.dense_sketch_matrix(m, k, "gaussian", 1).astype(np.float32)).to(dev)
+        y = torch.rand((b, k, L), device=dev)
+        r = torch.rand((b, m, L), device=dev)
+        sy = torch.empty((b, m, L), device=dev)
+        st = torch.empty((b, k, L), device=dev)
+        t_s = time_us(lambda: ops.capi.call("skei_sketch_rows", ops._ptr(G), m, k, ops._ptr(y), b, L, ops._ptr(sy),
+                                            ops._stream()))
+        t_t = time_us(lambda: ops.capi.call("skei_sketch_rows_T", ops._ptr(G), m, k, ops._ptr(r), b, L, ops._ptr(st),
+                                            ops._stream()))
+        flops = 2.0 * m * k * L * b
+        nbytes = 4.0 * (m * k + (k + m) * L * b)
+        out["gemm"].append({"m": m, "n_rows": k, "row_len": L, "batch": b, "flops": flops, "bytes": nbytes,
+                            "S_us": round(t_s, 2), "ST_us": round(t_t, 2),
+                            "S_tflops": round(flops / (t_s * 1e-6) / 1e12, 2),
+                            "S_frac_mfma_fp32": round(flops / (t_s * 1e-6) / 1e12 / PEAK_FP32_TFLOPS, 4),
+                            "S_frac_hbm": round(nbytes / (t_s * 1e-6) / 1e9 / PEAK_HBM_GBS, 4)})
+    n, na, nd, m = 256, 360, 363, 90
+    geom = ops.Geometry(n, na, nd)
+    x0, y = ei_inputs(geom, dict(n=n, batch=1), dev)
+    ds = ops.DenseSketch(geom, synth.dense_sketch_matrix(m, na, "gaussian", 2))
+    sub = geom.sketch(synth.random_sketch(na, m))
+    rb = torch.empty((1, na, nd), device=dev)
+    sb = torch.empty((1, m, nd), device=dev)
+    t_dense = time_us(lambda: ops.sketch_rows_(ds, ops.radon_resid_(geom, x0, y, geom.full(), out=rb), out=sb))
+    t_sub = time_us(lambda: ops.radon_resid_(geom, x0, y, sub, out=sb))
+    out["mc_residual_256sq_m90"] = {"dense_us": round(t_dense, 2), "subsampled_us": round(t_sub, 2)}
     return out
 
 

@@ -114,6 +114,24 @@ int skei_radon_fwd(const skei_geom *g, const float *x, int batch,
 int skei_radon_resid(const skei_geom *g, const float *x, const float *y_full, int batch,
                      const int32_t *angle_idx, int m, float *r, void *stream);
 
+/* Dense measurement-space sketches (the Gaussian / Rademacher sketches of
+ * Sec. 2.3 and of the proof of Theorem 1), mixing whole projections:
+ * S = G (x) I_{N_det} for a dense G in R^{m x n_rows} (row-major, device
+ * float32, e.g. i.i.d. N(0, 1/m) or +-1/sqrt(m) entries so that
+ * E[S^T S] = I).  A dense sketch of the operator is then A_S = S A, with
+ * A_S x = skei_sketch_rows(G, A x) and A_S^T r = A^T skei_sketch_rows_T(G, r).
+ *   skei_sketch_rows:   y [batch][n_rows][row_len] -> out [batch][m][row_len],
+ *                       out[b][i][c] = sum_a G[i][a] y[b][a][c];
+ *   skei_sketch_rows_T: r [batch][m][row_len] -> out [batch][n_rows][row_len],
+ *                       out[b][a][c] = sum_i G[i][a] r[b][i][c].
+ * Computed on the matrix cores in float32 with float32 accumulation, in a
+ * fixed order (deterministic).  batch <= 65535.  Inputs and outputs must not
+ * overlap. */
+int skei_sketch_rows(const float *G, int m, int n_rows, const float *y, int batch, int row_len,
+                     float *out, void *stream);
+int skei_sketch_rows_T(const float *G, int m, int n_rows, const float *r, int batch, int row_len,
+                       float *out, void *stream);
+
 /* x = A_S^T y   (exact transpose of skei_radon_fwd, computed per pixel as a
  * gather over the m listed angles: no atomics).
  * y [batch][m][N_det] -> x [batch][N][N]. */

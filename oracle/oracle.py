@@ -22,7 +22,7 @@ LIB_PATH = os.environ.get("SKEI_ORACLE_LIB") or os.path.join(_BUILD, "libskei_or
 
 __all__ = [
     "build", "radon_fwd", "radon_adj", "ramlak_tap", "ramp", "backproject",
-    "backproject_T", "fbp", "fbp_adj", "rotate", "rotate_adj", "ei_loss_grad",
+    "backproject_T", "fbp", "fbp_adj", "rotate", "rotate_adj", "ei_loss_grad", "sketch_rows", "sketch_rows_T",
     "num_threads", "LIB_PATH",
 ]
 
@@ -247,3 +247,30 @@ def ei_loss_grad(x, y, n_angles, idx, cos_sin, lam=1.0, mc_idx=None, want_grad=T
     if g is not None and sq:
         g = g[0]
     return loss, g
+
+
+def sketch_rows(G, y):
+    """Dense measurement-space sketch S = G (x) I applied to sinograms: the
+    Gaussian / Rademacher sketches of Sec. 2.3 acting on whole projections.
+    out[b][i][c] = sum_a G[i][a] y[b][a][c]; G [m, n_rows], y [n_rows, L] or
+    [B, n_rows, L].  Float64 matrix products."""
+    G = _d(G)
+    y = _d(y)
+    sq = y.ndim == 2
+    y3 = y[None] if sq else y
+    if y3.shape[1] != G.shape[1]:
+        raise ValueError("rows of y must match the columns of G")
+    out = np.stack([G @ y3[b] for b in range(y3.shape[0])])
+    return out[0] if sq else out
+
+
+def sketch_rows_T(G, r):
+    """The transpose S^T: out[b][a][c] = sum_i G[i][a] r[b][i][c]."""
+    G = _d(G)
+    r = _d(r)
+    sq = r.ndim == 2
+    r3 = r[None] if sq else r
+    if r3.shape[1] != G.shape[0]:
+        raise ValueError("rows of r must match the rows of G")
+    out = np.stack([G.T @ r3[b] for b in range(r3.shape[0])])
+    return out[0] if sq else out

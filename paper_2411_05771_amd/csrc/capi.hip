@@ -322,6 +322,22 @@ int skei_radon_resid(const skei_geom *g, const float *x, const float *y_full, in
     return launch_radon_fwd(g, x, nullptr, batch, angle_idx, m, r, y_full, g->tune_fwd, S(stream));
 }
 
+int skei_sketch_rows(const float *G, int m, int n_rows, const float *y, int batch, int row_len, float *out,
+                     void *stream)
+{
+    if (!G || !y || !out || m <= 0 || n_rows <= 0 || batch <= 0 || row_len <= 0) return SKEI_EINVAL;
+    if (batch > 65535 || (long long)m * n_rows > 0x7fffffffLL) return SKEI_ERANGE;
+    return launch_sketch_rows(G, m, n_rows, y, batch, row_len, false, out, S(stream));
+}
+
+int skei_sketch_rows_T(const float *G, int m, int n_rows, const float *r, int batch, int row_len, float *out,
+                       void *stream)
+{
+    if (!G || !r || !out || m <= 0 || n_rows <= 0 || batch <= 0 || row_len <= 0) return SKEI_EINVAL;
+    if (batch > 65535 || (long long)m * n_rows > 0x7fffffffLL) return SKEI_ERANGE;
+    return launch_sketch_rows(G, m, n_rows, r, batch, row_len, true, out, S(stream));
+}
+
 int skei_radon_adj(const skei_geom *g, const float *y, int batch, const int32_t *angle_idx, int m, float *x,
                    void *stream)
 {

@@ -312,6 +312,10 @@ RampJob make_row_sumsq_job(const struct ::skei_geom *g, const float *p, long lon
 RampJob make_loss_job(const RedJob &r);
 int ramp_block(int n_det);      // threads per row
 size_t ramp_shm(int n_det);     // LDS bytes per row
+// Dense sketch of sinogram rows (k_sketch.hip): out = G y per image, or
+// G^T y with transpose; G is m x n_rows row-major.
+int launch_sketch_rows(const float *G, int m, int n_rows, const float *y, int batch, int row_len, bool transpose,
+                       float *out, hipStream_t st);
 // Host walks of the LDS reads of the ramp and ray kernels (bounds self-checks).
 void ramp_lds_reads(int n_det, long long out[5]);
 void ray_lds_reads(int n, long long out[3]);

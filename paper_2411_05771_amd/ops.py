@@ -155,6 +155,45 @@ def radon_resid_(geom: Geometry, x: torch.Tensor, y_full: torch.Tensor, sk: Sket
     return r if x.dim() == 3 else r[0]
 
 
+class DenseSketch:
+    """A dense measurement-space sketch S = G (x) I_{N_det} (Sec. 2.3): G in
+    R^{m x N_theta} mixes whole projections (Gaussian or Rademacher entries,
+    see synth.dense_sketch_matrix).  Kept on the device as float32."""
+
+    def __init__(self, geom: Geometry, G):
+        g = np.ascontiguousarray(np.asarray(G, dtype=np.float32))
+        if g.ndim != 2 or g.shape[1] != geom.n_angles:
+            raise ValueError(f"G must be [m, {geom.n_angles}]")
+        self.geom = geom
+        self.m = g.shape[0]
+        self.dev = torch.from_numpy(g).to(geom.device)
+
+
+def sketch_rows_(ds: DenseSketch, y: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """S y: [B, N_theta, L] -> [B, m, L] on the matrix cores (skei_sketch_rows)."""
+    _check(y, torch.float32, ds.geom.device, "y")
+    y3 = y.unsqueeze(0) if y.dim() == 2 else y
+    if y3.dim() != 3 or y3.shape[1] != ds.dev.shape[1]:
+        raise ValueError(f"y must be [B, {ds.dev.shape[1]}, L]")
+    b, k, L = y3.shape
+    o = torch.empty((b, ds.m, L), device=y.device, dtype=torch.float32) if out is None else out
+    capi.call("skei_sketch_rows", _ptr(ds.dev), ds.m, k, _ptr(y3), b, L, _ptr(o), _stream())
+    return o if y.dim() == 3 else o[0]
+
+
+def sketch_rows_T_(ds: DenseSketch, r: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """S^T r: [B, m, L] -> [B, N_theta, L] (skei_sketch_rows_T)."""
+    _check(r, torch.float32, ds.geom.device, "r")
+    r3 = r.unsqueeze(0) if r.dim() == 2 else r
+    if r3.dim() != 3 or r3.shape[1] != ds.m:
+        raise ValueError(f"r must be [B, {ds.m}, L]")
+    b, _, L = r3.shape
+    k = ds.dev.shape[1]
+    o = torch.empty((b, k, L), device=r.device, dtype=torch.float32) if out is None else out
+    capi.call("skei_sketch_rows_T", _ptr(ds.dev), ds.m, k, _ptr(r3), b, L, _ptr(o), _stream())
+    return o if r.dim() == 3 else o[0]
+
+
 def radon_adj_(geom: Geometry, y: torch.Tensor, sk: Sketch, out: torch.Tensor | None = None) -> torch.Tensor:
     y3 = _sino(geom, y, sk.m)
     b = y3.shape[0]
@@ -293,6 +332,18 @@ class RadonResid(torch.autograd.Function):
         return -radon_adj_(ctx.geom, gr.contiguous(), ctx.sk), None, None, None
 
 
+class SketchRows(torch.autograd.Function):
+    """y -> S y for a dense sketch; the backward is S^T."""
+    @staticmethod
+    def forward(ctx, y, ds):
+        ctx.ds = ds
+        return sketch_rows_(ds, y.contiguous())
+
+    @staticmethod
+    def backward(ctx, g):
+        return sketch_rows_T_(ctx.ds, g.contiguous()), None
+
+
 class RadonAdj(torch.autograd.Function):
     @staticmethod
     def forward(ctx, y, geom, sk):
@@ -346,6 +397,24 @@ def radon_fwd(x, geom: Geometry, idx=None):
 def radon_resid(x, y_full, geom: Geometry, idx=None):
     """S y - A_S x (differentiable in x; y_full is the whole sinogram)."""
     return RadonResid.apply(x, y_full, geom, _as_sketch(geom, idx))
+
+
+def sketch_rows(y, ds: DenseSketch):
+    """S y for a dense sketch (differentiable)."""
+    return SketchRows.apply(y, ds)
+
+
+def radon_resid_dense(x, y_full, geom: Geometry, ds: DenseSketch):
+    """S (y - A x) for a dense sketch (differentiable in x): the residual is
+    formed in double by skei_radon_resid before the mixing, so the sketch of
+    a residual ~100x smaller than y keeps its digits."""
+    return SketchRows.apply(RadonResid.apply(x, y_full, geom, geom.full()), ds)
+
+
+def radon_fwd_dense(x, geom: Geometry, ds: DenseSketch):
+    """The densely sketched operator A_S x = S (A x) (differentiable): every
+    angle is projected, then the projections are mixed by G."""
+    return SketchRows.apply(RadonFwd.apply(x, geom, geom.full()), ds)
 
 
 def radon_adj(y, geom: Geometry, idx=None):

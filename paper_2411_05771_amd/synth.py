@@ -148,3 +148,15 @@ def poisson_jobs(count: int, rate: float, sizes=(256, 512, 1024), angles=(180, 1
                         m=max(1, na // ratio), copies=copies, iters=iters, phantom_seed=SEED_PHANTOM + 7919 * (i + 1),
                         rotation_seed=SEED_ROTATION + 7919 * (i + 1), noise_seed=SEED_NOISE + 7919 * (i + 1)))
     return out
+
+
+def dense_sketch_matrix(m: int, n_rows: int, kind: str = "gaussian", seed: int = SEED_SKETCH) -> np.ndarray:
+    """A dense sketch G in R^{m x n_rows} (float64): i.i.d. N(0, 1/m) entries
+    ("gaussian") or +-1/sqrt(m) with equal probability ("rademacher"), so
+    that E[G^T G] = I.  Seeded; passed to both the library and the oracle."""
+    g = rng(seed)
+    if kind == "gaussian":
+        return g.standard_normal((m, n_rows)) / np.sqrt(m)
+    if kind == "rademacher":
+        return np.where(g.integers(0, 2, size=(m, n_rows)) == 1, 1.0, -1.0) / np.sqrt(m)
+    raise ValueError("kind is 'gaussian' or 'rademacher'")
