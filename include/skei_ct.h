@@ -339,8 +339,12 @@ int skei_probe_set(int stage, void *ev_begin, void *ev_end);
  *     thread, last element of the staged row, elements allocated (doubles).
  *   SKEI_LDS_RAY, size = N (2..2032): out[0..2] = lowest and highest
  *     position read within a staged image line, and the line pitch (floats).
+ *   SKEI_LDS_GATHER, size = N (2..2032): out[0..2] = lowest and highest
+ *     window bin read by the pixel-driven gathers (the interpolation
+ *     neighbour included) over every 16 x 16 tile and the angles of 7- and
+ *     360-angle tables, and the window length (bins).
  * Returns SKEI_EINVAL / SKEI_ERANGE for a bad kernel or size. */
-enum { SKEI_LDS_RAMP = 0, SKEI_LDS_RAY = 1 };
+enum { SKEI_LDS_RAMP = 0, SKEI_LDS_RAY = 1, SKEI_LDS_GATHER = 2 };
 int skei_lds_read_bounds(int kernel, int size, long long *out);
 
 #ifdef __cplusplus

@@ -293,6 +293,11 @@ int skei_lds_read_bounds(int kernel, int size, long long *out)
         ray_lds_reads(size, out);
         return SKEI_OK;
     }
+    if (kernel == SKEI_LDS_GATHER) {
+        if (size > 2032) return SKEI_ERANGE;
+        gather_lds_reads(size, out);
+        return SKEI_OK;
+    }
     return SKEI_EINVAL;
 }
 

@@ -87,6 +87,8 @@ int skei_geom_create(int n, int n_angles, int n_det, skei_geom **out)
         r.base_fx = (int64_t)std::llround(base * two32);
         r.inv_fx = (int64_t)std::llround(two32 / cm);
         r.du_fx = (int64_t)std::llround(-cM / cm * two32);
+        r.c_fx = (int64_t)std::llround(c * two32);
+        r.s_fx = (int64_t)std::llround(s * two32);
         r.cd = c;
         r.sd = s;
         r.c = (float)c;

@@ -22,6 +22,7 @@ struct AngleRow {
     int64_t base_fx;  // base, inv_m and du in 32.32 fixed point (exact ray stepping)
     int64_t inv_fx;
     int64_t du_fx;
+    int64_t c_fx, s_fx;   // cos theta, sin theta in 32.32 (pixel-driven positions)
     double scale;     // 1 / |c_m|   (Joseph step length), double
     double cd, sd;    // cos theta, sin theta in double (pixel-driven positions)
     float c, s;       // cos theta, sin theta
@@ -32,7 +33,7 @@ struct AngleRow {
     float inv_m;      // 1 / c_m
     int rows;         // 1: major axis = image rows
 };
-static_assert(sizeof(AngleRow) == 80, "AngleRow layout");
+static_assert(sizeof(AngleRow) == 96, "AngleRow layout");
 
 // LDS line padding used by the ray-driven kernels: every staged image line
 // carries PAD zeros on each side so that clamped tap positions read zeros.
@@ -319,6 +320,7 @@ int launch_sketch_rows(const float *G, int m, int n_rows, const float *y, int ba
 // Host walks of the LDS reads of the ramp and ray kernels (bounds self-checks).
 void ramp_lds_reads(int n_det, long long out[5]);
 void ray_lds_reads(int n, long long out[3]);
+void gather_lds_reads(int n, long long out[3]);
 
 RotJob make_rot_job(const float *x, int batch, int copies, int n, const float *cs, float *out, float *outT);
 RotAdjJob make_rot_adj_job(const float *h, int batch, int copies, int n, const float *cs, float alpha,

@@ -6,7 +6,11 @@ lie past the row end, which read beyond the row into the partial-sum area --
 stays inside the allocation, and threads that own an output read only the
 staged row, for every detector count the library accepts (2..2048).
 Ray march: clamped tap positions stay inside the padded line for every image
-size (2..2032)."""
+size (2..2032).
+Gathers: the fixed-point pixel positions of every 16 x 16 tile fall in
+window bins 0 .. 31 (with the interpolation neighbour) for every angle of a
+7- and a 360-angle table, at small and full detector counts, for image sizes
+across the range (ragged tiles, powers of two and the maximum 2032)."""
 import ctypes
 
 import pytest
@@ -36,6 +40,12 @@ def test_ray_taps_stay_in_padded_line(hiplib):
     for n in range(2, 2033):
         lo, hi, pitch = bounds(1, n, 3)
         assert lo >= 0 and hi < pitch, n
+
+
+@pytest.mark.parametrize("n", [2, 3, 15, 16, 17, 31, 33, 64, 100, 255, 256, 257, 511, 512, 1000, 1024, 2032])
+def test_gather_positions_stay_in_window(hiplib, n):
+    lo, hi, win = bounds(2, n, 3)
+    assert lo >= 0 and hi <= win - 1, (n, lo, hi)
 
 
 def test_layout_walk_rejects_bad_arguments(hiplib):
