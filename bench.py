@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the uneven 64-problem leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-ttt", action="store_true", help="skip the test-time-training leg")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time the headline EI step only (no further legs), e.g. under a profiler")
     ap.add_argument("--serve-jobs", type=int, default=12)
     ap.add_argument("--serve-rates", default="1,2,3,4,8", help="Poisson arrival rates swept, jobs per second")
     ap.add_argument("--serve-jobs-small", type=int, default=24)
@@ -245,15 +247,16 @@ def main():
             gather_equiv_bytes(dominant, w, widths, widths_mc) / (dom_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
     }
     plan.close()
-    out["plain_ops"] = plain_ops_leg()
-    out["paper_shaped"] = paper_shaped_leg()
-    out["dense_sketch"] = dense_sketch_leg()
-    if not args.no_ttt:
-        out["ttt"] = ttt_leg()
-    if not args.no_batched:
-        out["batched"] = batched_leg(args)
-    if not args.no_serving:
-        out["serving"] = serving_leg(args)
+    if not args.headline_only:
+        out["plain_ops"] = plain_ops_leg()
+        out["paper_shaped"] = paper_shaped_leg()
+        out["dense_sketch"] = dense_sketch_leg()
+        if not args.no_ttt:
+            out["ttt"] = ttt_leg()
+        if not args.no_batched:
+            out["batched"] = batched_leg(args)
+        if not args.no_serving:
+            out["serving"] = serving_leg(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["parity"] = cpu_baseline(w, idx, args.cpu_seconds, rays_per_step)
     print(json.dumps(out), flush=True)
@@ -631,12 +634,17 @@ def traffic_for(stage, shape):
         return None, None
 
 
+# The sources the ray kernels (the forward and B^T stages whose traffic the
+# counters measured) are built from: their kernels, the job and angle-table
+# layouts and the angle table's construction.
+RAY_KERNEL_SOURCES = ("k_project.hip", "skei_internal.h", "work.h", "geom.hip")
+
+
 def source_sha():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2411_05771_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in RAY_KERNEL_SOURCES:
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
