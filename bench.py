@@ -63,6 +63,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the uneven 64-problem leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-ttt", action="store_true", help="skip the test-time-training leg")
+    ap.add_argument("--no-mri", action="store_true", help="skip the multicoil MRI leg")
     ap.add_argument("--headline-only", action="store_true",
                     help="time the headline EI step only (no further legs), e.g. under a profiler")
     ap.add_argument("--serve-jobs", type=int, default=12)
@@ -253,6 +254,8 @@ def main():
         out["dense_sketch"] = dense_sketch_leg()
         if not args.no_ttt:
             out["ttt"] = ttt_leg()
+        if not args.no_mri:
+            out["mri"] = mri_leg()
         if not args.no_batched:
             out["batched"] = batched_leg(args)
         if not args.no_serving:
@@ -458,6 +461,92 @@ def ttt_leg():
     out["paper_context"] = {"hardware": "RTX 4060 Ti", "time_per_epoch_s_full_ei": 9.56,
                             "time_per_epoch_s_skei_50_20_10_5pct": [2.66, 1.34, 1.25, 1.18],
                             "bn_only_full_ei": 5.45, "bn_only_skei_50_20_10_5pct": [1.46, 1.09, 1.00, 0.95]}
+    return out
+
+
+def mri_leg():
+    """Multicoil MRI with coil sketches (Sec. 3.4, Algorithm 3) at the paper's
+    setup: 128 x 128 images, 15 coils, 4x Cartesian undersampling (8 % of
+    the rows around the zero frequency kept), synthetic maps, phantom and
+    0.5 % noise.  Per-call time of A and A^H, and the wall time of one
+    sketched EI iteration (loss, backward, Adam step; one whole-degree
+    rotation per iteration), device-synchronised, for the full operator, the
+    classical sketch (a random subset of Mc coils drawn every iteration, its
+    operator and data formed by the library's coil selection) and the coil
+    sketch (covariance, PCA to L = 15 virtual coils, R = ceil(Mc / 2) kept,
+    Rademacher mixing of the rest; one fixed sketch, set-up timed apart),
+    Mc in {10, 5, 2}; with the network taken as the identity (the
+    operators' part) and with the residual BN U-Net (2 channels, widths
+    32-256) as F, adapted in full."""
+    import torch
+
+    from paper_2411_05771_amd import mri, synth, ttt
+    dev = torch.device("cuda", 0)
+    n, nc = 128, 15
+    prob = mri.MRIProblem(n=n, nc=nc, accel=4, noise=0.005, device=dev)
+    op, y = prob.op, prob.y
+    rot = ttt.rotation_table(dev)
+    g = synth.rng(synth.SEED_MRI + 50)
+
+    def t_us(fn, reps=100):
+        for _ in range(5):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return round(e0.elapsed_time(e1) * 1e3 / reps, 2)
+
+    out = {"workload": "mri_128sq_15coils_4x", "operator_us": {
+        "A": t_us(lambda: op.fwd_(prob.x0)), "A_H": t_us(lambda: op.adj_(y)), "A_pinv": t_us(lambda: op.pinv_(y))}}
+
+    def sketch_for(kind, mc):
+        if kind == "full":
+            return lambda: (op, y)
+        if kind == "classical":
+            return lambda: mri.classical_sketch(op, y, g.choice(nc, size=mc, replace=False))
+        op_s, y_s, _ = mri.coil_sketch(op, y, nc, (mc + 1) // 2, mc)
+        return lambda: (op_s, y_s)
+
+    def run(kind, mc, net):
+        get = sketch_for(kind, mc)
+        if net is None:
+            x = prob.x0.clone().requires_grad_(True)
+            opt = torch.optim.Adam([x], lr=5e-4)
+        else:
+            x = None
+            opt = torch.optim.Adam(net.parameters(), lr=5e-4)
+
+        def step():
+            o, ys = get()
+            i = int(g.integers(360))
+            opt.zero_grad(set_to_none=True)
+            if net is None:
+                loss, _, _ = mri.mri_ei_loss(x, ys, o, rot[i:i + 1])
+            else:
+                loss, _, _ = mri.mri_skei_ttt_loss(net, prob.x0, ys, o, rot[i:i + 1])
+            loss.backward()
+            opt.step()
+        return round(1e3 * mri.time_per_iteration(step, iters=30, warmup=5), 3)
+
+    cases = [("full", nc)] + [(k, mc) for k in ("classical", "coil") for mc in (10, 5, 2)]
+    setup = {}
+    for mc in (10, 5, 2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mri.coil_sketch(op, y, nc, (mc + 1) // 2, mc)
+        torch.cuda.synchronize()
+        setup[f"coil_Mc{mc}"] = round((time.perf_counter() - t0) * 1e3, 3)
+    out["coil_sketch_setup_ms"] = setup
+    out["identity_ms_per_iteration"] = {f"{k}_Mc{mc}": run(k, mc, None) for k, mc in cases}
+    torch.manual_seed(0)
+    base = ttt.ResUNet(width=32, depth=4, channels=2).to(dev)
+    import copy
+    out["unet_ms_per_iteration"] = {f"{k}_Mc{mc}": run(k, mc, copy.deepcopy(base)) for k, mc in cases}
+    out["paper_context"] = {"hardware": "RTX 4060 Ti", "s_per_iteration_full_ei": 0.157,
+                            "c_skei_10_5_2": [0.151, 0.134, 0.130], "skei_10_5_2": [0.141, 0.129, 0.127]}
     return out
 
 

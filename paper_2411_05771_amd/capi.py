@@ -50,6 +50,15 @@ _SIGS = {
     "skei_radon_resid": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_int, c_void_p, c_void_p]),
     "skei_sketch_rows": (c_int, [c_void_p, c_int, c_int, c_void_p, c_int, c_int, c_void_p, c_void_p]),
     "skei_sketch_rows_T": (c_int, [c_void_p, c_int, c_int, c_void_p, c_int, c_int, c_void_p, c_void_p]),
+    # multicoil MRI (include/skei_mri.h)
+    "skei_mri_fwd": (c_int, [c_void_p, c_int, c_int, c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "skei_mri_adj": (c_int, [c_void_p, c_int, c_int, c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
+                             c_void_p]),
+    "skei_mri_work_bytes": (c_size_t, [c_int, c_int, c_int]),
+    "skei_coil_weights": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p]),
+    "skei_coil_mix": (c_int, [c_void_p, c_int, c_int, c_void_p, c_int, ctypes.c_longlong, c_void_p, c_void_p]),
+    "skei_coil_covariance": (c_int, [c_void_p, c_int, ctypes.c_longlong, c_void_p, c_void_p]),
+    "skei_coil_pca": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p]),
     "skei_ramp": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_void_p]),
     "skei_backproject": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_int, c_void_p, c_void_p]),
     "skei_backproject_T": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_int, c_void_p, c_void_p]),

@@ -160,3 +160,63 @@ def dense_sketch_matrix(m: int, n_rows: int, kind: str = "gaussian", seed: int =
     if kind == "rademacher":
         return np.where(g.integers(0, 2, size=(m, n_rows)) == 1, 1.0, -1.0) / np.sqrt(m)
     raise ValueError("kind is 'gaussian' or 'rademacher'")
+
+
+# ---------------------------------------------------------------- multicoil MRI
+SEED_MRI = 7000
+
+
+def coil_maps(nc: int, n: int, seed: int = SEED_MRI) -> np.ndarray:
+    """Smooth synthetic coil sensitivities [nc, n, n] complex128: Gaussian
+    profiles centred on a ring around the field of view (radius 0.6 n, width
+    0.35 n, small random jitter), each with a smooth linear phase, then
+    normalised so that sum_c |C_c|^2 = 1 at every pixel.  They stand in for
+    the ESPIRiT maps of measured data."""
+    g = rng(seed)
+    yy, xx = np.mgrid[0:n, 0:n].astype(np.float64)
+    c0 = 0.5 * (n - 1)
+    maps = np.empty((nc, n, n), dtype=np.complex128)
+    for c in range(nc):
+        th = 2.0 * math.pi * c / nc + g.uniform(-0.1, 0.1)
+        cx, cy = c0 + 0.6 * n * math.cos(th), c0 + 0.6 * n * math.sin(th)
+        sig = 0.35 * n * g.uniform(0.9, 1.1)
+        mag = np.exp(-((xx - cx) ** 2 + (yy - cy) ** 2) / (2.0 * sig * sig))
+        ph = g.uniform(-math.pi, math.pi) + (g.uniform(-1.0, 1.0) * xx + g.uniform(-1.0, 1.0) * yy) * math.pi / n
+        maps[c] = mag * np.exp(1j * ph)
+    return maps / np.sqrt(np.sum(np.abs(maps) ** 2, axis=0))[None]
+
+
+def complex_phantom(n: int, seed: int) -> np.ndarray:
+    """An ellipse phantom with a smooth random phase, [n, n] complex128."""
+    g = rng(seed + 1)
+    yy, xx = np.mgrid[0:n, 0:n].astype(np.float64) / n
+    ph = g.uniform(-1.0, 1.0) * xx + g.uniform(-1.0, 1.0) * yy + g.uniform(-0.5, 0.5) * xx * yy
+    return ellipse_phantom(n, seed, dtype=np.float64) * np.exp(1j * math.pi * ph)
+
+
+def cartesian_mask(n: int, accel: int = 4, center_frac: float = 0.08, seed: int = SEED_MRI) -> np.ndarray:
+    """Cartesian undersampling of the phase-encode (row) direction at
+    acceleration `accel` (n / accel rows kept): every row within
+    center_frac * n of the zero frequency (the rows near index 0 and n - 1
+    of the unshifted DFT grid), the rest drawn at random; [n, n] float64 0/1."""
+    g = rng(seed + 2)
+    keep = max(1, n // accel)
+    nc = max(1, min(keep, int(round(center_frac * n))))
+    freq = np.minimum(np.arange(n), n - np.arange(n))      # |frequency| of each row
+    centre = np.argsort(freq, kind="stable")[:nc]
+    rest = np.setdiff1d(np.arange(n), centre)
+    rows = np.concatenate([centre, g.choice(rest, size=keep - nc, replace=False)])
+    mask = np.zeros((n, n))
+    mask[rows] = 1.0
+    return mask
+
+
+def rademacher_signs(rows: int, cols: int, seed: int = SEED_MRI) -> np.ndarray:
+    """i.i.d. +-1 entries with equal probability, [rows, cols] float64."""
+    return np.where(rng(seed + 3).integers(0, 2, size=(rows, cols)) == 1, 1.0, -1.0)
+
+
+def complex_noise(shape, seed: int) -> np.ndarray:
+    """Standard complex Gaussian noise (independent N(0, 1/2) parts)."""
+    g = rng(seed)
+    return (g.standard_normal(shape) + 1j * g.standard_normal(shape)) / math.sqrt(2.0)

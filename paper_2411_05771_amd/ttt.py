@@ -44,16 +44,17 @@ class _Block(nn.Module):
 
 
 class ResUNet(nn.Module):
-    """A residual U-Net with BatchNorm: F(x) = x + U(x) for one-channel
-    images whose side is a multiple of 2^(depth-1)."""
+    """A residual U-Net with BatchNorm: F(x) = x + U(x) for images of
+    `channels` channels (1 for CT, 2 -- real and imaginary parts -- for MRI)
+    whose side is a multiple of 2^(depth-1)."""
 
-    def __init__(self, width: int = 32, depth: int = 4):
+    def __init__(self, width: int = 32, depth: int = 4, channels: int = 1):
         super().__init__()
         ch = [width * 2 ** i for i in range(depth)]
-        self.down = nn.ModuleList([_Block(1 if i == 0 else ch[i - 1], ch[i]) for i in range(depth)])
+        self.down = nn.ModuleList([_Block(channels if i == 0 else ch[i - 1], ch[i]) for i in range(depth)])
         self.up = nn.ModuleList([nn.ConvTranspose2d(ch[i], ch[i - 1], 2, stride=2) for i in range(depth - 1, 0, -1)])
         self.dec = nn.ModuleList([_Block(2 * ch[i - 1], ch[i - 1]) for i in range(depth - 1, 0, -1)])
-        self.out = nn.Conv2d(ch[0], 1, 1)
+        self.out = nn.Conv2d(ch[0], channels, 1)
         self.pool = nn.MaxPool2d(2)
 
     def forward(self, x):

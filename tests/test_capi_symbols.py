@@ -1,17 +1,19 @@
-"""The C-ABI library loads and exports every entry point include/skei_ct.h declares.
+"""The C-ABI library loads and exports every entry point include/*.h declares
+(skei_ct.h: the CT operators; skei_mri.h: the multicoil MRI operator).
 
 No compute call is made here (this runs without a GPU)."""
 import ctypes
+import glob
 import os
 import re
 import subprocess
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "skei_ct.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 def declared():
-    text = open(HEADER).read()
+    text = "\n".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"^[A-Za-z_][\w \*]*?\b(skei_\w+)\s*\(", text, flags=re.M)))
 
@@ -19,7 +21,8 @@ def declared():
 def test_header_declares_the_expected_boundary():
     names = declared()
     for must in ("skei_geom_create", "skei_radon_fwd", "skei_radon_adj", "skei_radon_resid", "skei_fbp", "skei_fbp_adj",
-                 "skei_rotate", "skei_rotate_adj", "skei_ei_loss_grad", "skei_strerror"):
+                 "skei_rotate", "skei_rotate_adj", "skei_ei_loss_grad", "skei_strerror", "skei_mri_fwd",
+                 "skei_mri_adj", "skei_coil_mix", "skei_coil_covariance", "skei_coil_pca"):
         assert must in names
 
 
