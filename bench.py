@@ -66,6 +66,9 @@ def parse():
     ap.add_argument("--no-mri", action="store_true", help="skip the multicoil MRI leg")
     ap.add_argument("--headline-only", action="store_true",
                     help="time the headline EI step only (no further legs), e.g. under a profiler")
+    ap.add_argument("--legs", default=None,
+                    help="comma list of the further legs to run (plain_ops, paper_shaped, dense_sketch, ttt, mri, "
+                         "batched, serving); default: all, minus the --no-* ones")
     ap.add_argument("--serve-jobs", type=int, default=12)
     ap.add_argument("--serve-rates", default="1,2,3,4,8", help="Poisson arrival rates swept, jobs per second")
     ap.add_argument("--serve-jobs-small", type=int, default=24)
@@ -249,16 +252,28 @@ def main():
     }
     plan.close()
     if not args.headline_only:
-        out["plain_ops"] = plain_ops_leg()
-        out["paper_shaped"] = paper_shaped_leg()
-        out["dense_sketch"] = dense_sketch_leg()
-        if not args.no_ttt:
+        legs = {"plain_ops": True, "paper_shaped": True, "dense_sketch": True, "ttt": not args.no_ttt,
+                "mri": not args.no_mri, "batched": not args.no_batched, "serving": not args.no_serving}
+        if args.legs is not None:
+            chosen = {v.strip() for v in args.legs.split(",") if v.strip()}
+            unknown = chosen - set(legs)
+            if unknown:
+                print(f"unknown legs: {sorted(unknown)}", file=sys.stderr)
+                sys.exit(2)
+            legs = {k: k in chosen for k in legs}
+        if legs["plain_ops"]:
+            out["plain_ops"] = plain_ops_leg()
+        if legs["paper_shaped"]:
+            out["paper_shaped"] = paper_shaped_leg()
+        if legs["dense_sketch"]:
+            out["dense_sketch"] = dense_sketch_leg()
+        if legs["ttt"]:
             out["ttt"] = ttt_leg()
-        if not args.no_mri:
+        if legs["mri"]:
             out["mri"] = mri_leg()
-        if not args.no_batched:
+        if legs["batched"]:
             out["batched"] = batched_leg(args)
-        if not args.no_serving:
+        if legs["serving"]:
             out["serving"] = serving_leg(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["parity"] = cpu_baseline(w, idx, args.cpu_seconds, rays_per_step)
