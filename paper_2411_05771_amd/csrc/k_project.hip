@@ -479,14 +479,14 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
                     const int ub = max(ulo[0], M0), ue = min(whi, M0 + Rc - 1);
                     if (resid) {
                         // residual jobs: each line's lerp in float, four lines
-                        // (aligned) summed in float, then added in double; the
-                        // groups are not unrolled, so this loop needs no more
-                        // registers than the one below
+                        // (aligned) summed in float, then added in double; a
+                        // unit's groups are unrolled (measured on MI355X: the
+                        // headline forward 70.2 -> 67.6 us, one spilled VGPR)
 #pragma unroll 1
                         for (int Mb = ub; Mb <= ue; Mb += U) {
                             // entry j of line Mb + l sits at index j + kBias of `line`
                             const float *ubase = chunk + (Mb - M0) * pitch + kLinePad - kBias;
-#pragma unroll 1
+#pragma unroll
                             for (int l4 = 0; l4 < U; l4 += 4) {
                                 float v4[RPT];
 #pragma unroll
