@@ -12,8 +12,8 @@
 // A workgroup of four waves owns a 64 x 64 tile of one image's output (each
 // wave a 16-row strip) or, when that gives too few workgroups to fill the
 // chip, a 32 x 32 tile (each wave a 16 x 16 quarter).  K runs in chunks of
-// 32: both operand tiles are staged in LDS (zero-filled past the edges), then
-// the waves issue their MFMAs.  The left matrix is read
+// 32: both operand tiles are staged in LDS (zero-filled past the edges), the
+// next chunk's loads in flight while the waves issue the current one's MFMAs.  The left matrix is read
 // through strides (G row-major for S, its transpose for S^T).
 #include "skei_internal.h"
 
@@ -47,18 +47,48 @@ __global__ void __launch_bounds__(256) k_sketch_rows(const float *__restrict__ G
 #pragma unroll
         for (int j = 0; j < BC; j++) acc[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 
-    for (int k0 = 0; k0 < K; k0 += kKc) {
-        for (int e = tid; e < TM * kKc; e += 256) {
-            const int r = e / kKc, k = e % kKc;
+    // Chunk k0's operands are loaded into registers while chunk k0 - kKc is
+    // multiplied out of LDS, then stored to LDS behind a barrier.  Left
+    // elements are assigned so that consecutive threads read consecutive
+    // addresses of G (along k for S, along r for S^T).
+    constexpr int NA = TM * kKc / 256, NB = kKc * TN / 256;
+    const bool a_along_k = g_col == 1;
+    float ra[NA], rb[NB];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < NA; i++) {
+            const int e = tid + 256 * i;
+            const int r = a_along_k ? e / kKc : e % TM, k = a_along_k ? e % kKc : e / TM;
             const int gr = r0 + r, gk = k0 + k;
-            As[r][k] = (gr < M && gk < K) ? G[gr * g_row + gk * g_col] : 0.0f;
+            ra[i] = (gr < M && gk < K) ? G[gr * g_row + gk * g_col] : 0.0f;
         }
-        for (int e = tid; e < kKc * TN; e += 256) {
+#pragma unroll
+        for (int i = 0; i < NB; i++) {
+            const int e = tid + 256 * i;
             const int k = e / TN, c = e % TN;
             const int gk = k0 + k, gc = c0 + c;
-            Bs[k][c] = (gk < K && gc < L) ? Yb[(size_t)gk * L + gc] : 0.0f;
+            rb[i] = (gk < K && gc < L) ? Yb[(size_t)gk * L + gc] : 0.0f;
         }
-        __syncthreads();
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int i = 0; i < NA; i++) {
+            const int e = tid + 256 * i;
+            const int r = a_along_k ? e / kKc : e % TM, k = a_along_k ? e % kKc : e / TM;
+            As[r][k] = ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < NB; i++) {
+            const int e = tid + 256 * i;
+            Bs[e / TN][e % TN] = rb[i];
+        }
+    };
+    load(0);
+    store();
+    __syncthreads();
+    for (int k0 = 0; k0 < K; k0 += kKc) {
+        const bool more = k0 + kKc < K;
+        if (more) load(k0 + kKc);
 #pragma unroll
         for (int kk = 0; kk < kKc; kk += 4) {
             float a[BR];
@@ -73,6 +103,10 @@ __global__ void __launch_bounds__(256) k_sketch_rows(const float *__restrict__ G
             }
         }
         __syncthreads();
+        if (more) {
+            store();
+            __syncthreads();
+        }
     }
     float *ob = out + (size_t)b * M * L;
 #pragma unroll
