@@ -491,8 +491,9 @@ def mri_leg():
     sketch (covariance, PCA to L = 15 virtual coils, R = ceil(Mc / 2) kept,
     Rademacher mixing of the rest; one fixed sketch, set-up timed apart),
     Mc in {10, 5, 2}; with the network taken as the identity (the
-    operators' part) and with the residual BN U-Net (2 channels, widths
-    32-256) as F, adapted in full."""
+    operators' part) -- eagerly and as one HIP graph replayed per iteration
+    (fixed operators only) -- and with the residual BN U-Net (2 channels,
+    widths 32-256) as F, adapted in full."""
     import torch
 
     from paper_2411_05771_amd import mri, synth, ttt
@@ -556,6 +557,16 @@ def mri_leg():
         setup[f"coil_Mc{mc}"] = round((time.perf_counter() - t0) * 1e3, 3)
     out["coil_sketch_setup_ms"] = setup
     out["identity_ms_per_iteration"] = {f"{k}_Mc{mc}": run(k, mc, None) for k, mc in cases}
+
+    # the same iteration (network = identity) captured once in a HIP graph and
+    # replayed, for the fixed operators (the full one and the coil sketches)
+    def run_graph(kind, mc):
+        o, ys = sketch_for(kind, mc)()
+        gs = mri.MRIGraphStep(prob.x0, ys, o)
+        return round(1e3 * mri.time_per_iteration(lambda: gs.step(rot[int(g.integers(360))].unsqueeze(0)),
+                                                   iters=50, warmup=5), 4)
+    out["identity_graph_ms_per_iteration"] = {f"{k}_Mc{mc}": run_graph(k, mc) for k, mc in cases
+                                              if k != "classical"}
     torch.manual_seed(0)
     base = ttt.ResUNet(width=32, depth=4, channels=2).to(dev)
     import copy

@@ -29,7 +29,7 @@ from . import capi, ops, synth
 __all__ = [
     "MRIOperator", "mri_fwd", "mri_pinv", "coil_mix_", "classical_sketch", "coil_sketch", "coil_covariance_",
     "coil_pca", "rotate_complex", "mri_ei_loss", "mri_skei_ttt_loss", "MRIProblem", "make_problem",
-    "time_per_iteration",
+    "time_per_iteration", "MRIGraphStep",
 ]
 
 
@@ -211,7 +211,32 @@ def rotate_complex(x: torch.Tensor, cs: torch.Tensor) -> torch.Tensor:
     return torch.complex(ops.rotate(x.real.contiguous(), cs), ops.rotate(x.imag.contiguous(), cs))
 
 
-def mri_ei_loss(x: torch.Tensor, y: torch.Tensor, op: MRIOperator, cs: torch.Tensor, lam: float = 1.0):
+class _SumSq(torch.autograd.Function):
+    """||r||^2 of a complex tensor (its real and imaginary parts), reduced in
+    double by the library in a fixed order (no atomics, no memset: the form
+    that HIP graph capture keeps correct on every replay)."""
+
+    @staticmethod
+    def forward(ctx, r):
+        rr = torch.view_as_real(r.contiguous()).reshape(-1)
+        ctx.save_for_backward(rr)
+        ctx.shape = r.shape
+        return ops.sumsq_diff_(rr)
+
+    @staticmethod
+    def backward(ctx, g):
+        (rr,) = ctx.saved_tensors
+        return torch.view_as_complex((rr * (2.0 * g).float()).reshape(-1, 2)).reshape(ctx.shape)
+
+
+def _sumsq(r, library: bool):
+    if library:
+        return _SumSq.apply(r)
+    return (torch.view_as_real(r).double() ** 2).sum()
+
+
+def mri_ei_loss(x: torch.Tensor, y: torch.Tensor, op: MRIOperator, cs: torch.Tensor, lam: float = 1.0,
+                library_sums: bool = False):
     """The sketched EI loss of Algorithm 3 with the network taken as the
     identity: sum_b ||y_b - A x_b||^2 + (lam / C) sum_{b,c} ||T_c x_b -
     A^dagger A T_c x_b||^2, for the (sketched) operator `op` and data y.
@@ -219,12 +244,12 @@ def mri_ei_loss(x: torch.Tensor, y: torch.Tensor, op: MRIOperator, cs: torch.Ten
     x3 = x if x.dim() == 3 else x.unsqueeze(0)
     y4 = y if y.dim() == 4 else y.unsqueeze(0)
     r_mc = y4 - mri_fwd(x3, op)
-    l_mc = (torch.view_as_real(r_mc).double() ** 2).sum()
+    l_mc = _sumsq(r_mc, library_sums)
     z = rotate_complex(x3, cs)                                   # [B,C,N,N]
     b, c = z.shape[0], z.shape[1]
     zf = z.reshape(b * c, op.n, op.n)
     r = zf - mri_pinv(mri_fwd(zf, op), op)
-    l_ei = (torch.view_as_real(r).double() ** 2).sum()
+    l_ei = _sumsq(r, library_sums)
     return l_mc + (lam / c) * l_ei, l_mc, l_ei
 
 
@@ -288,3 +313,57 @@ def time_per_iteration(step, iters: int = 20, warmup: int = 3) -> float:
         step()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / iters
+
+
+class MRIGraphStep:
+    """One EI iteration of Algorithm 3 with the network taken as the
+    identity -- loss, backward, Adam step on the image -- captured once in a
+    HIP graph and replayed.  The operator and data stay fixed (the full
+    operator or one coil sketch); each replay takes the rotation written
+    into a static (cos, sin) buffer beforehand.  Every kernel of the
+    iteration is one of the library's or an elementwise PyTorch kernel, and
+    the sums are the library's fixed-order reductions, so the graph holds no
+    memset node.  x is updated in place."""
+
+    def __init__(self, x0: torch.Tensor, y: torch.Tensor, op: MRIOperator, lam: float = 1.0, lr: float = 5e-4,
+                 warmup: int = 3):
+        self.x = x0.detach().clone().requires_grad_(True)
+        self.y, self.op, self.lam = y, op, lam
+        self.cs = torch.zeros((1, 2), device=x0.device, dtype=torch.float32)
+        self.cs[0, 0] = 1.0
+        self.opt = torch.optim.Adam([self.x], lr=lr, capturable=True)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for _ in range(warmup):
+                self._iteration()
+        torch.cuda.current_stream().wait_stream(side)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.loss = self._iteration()
+        self.reset(x0)
+
+    def reset(self, x0: torch.Tensor):
+        """Back to x0 with fresh Adam moments (the warm-up iterations moved
+        them); in place, so the captured graph keeps its addresses."""
+        with torch.no_grad():
+            self.x.copy_(x0)
+            for st in self.opt.state.values():
+                for v in st.values():
+                    if torch.is_tensor(v):
+                        v.zero_()
+
+    def _iteration(self):
+        self.opt.zero_grad(set_to_none=True)
+        loss, _, _ = mri_ei_loss(self.x, self.y, self.op, self.cs, self.lam, library_sums=True)
+        loss.backward()
+        self.opt.step()
+        return loss.detach()
+
+    def step(self, cos_sin: torch.Tensor):
+        """One iteration with the rotation cos_sin [1, 2]; returns the loss
+        (device scalar, valid after the stream reaches it)."""
+        self.cs.copy_(cos_sin)
+        self.graph.replay()
+        return self.loss
+
