@@ -491,8 +491,8 @@ def mri_leg():
     sketch (covariance, PCA to L = 15 virtual coils, R = ceil(Mc / 2) kept,
     Rademacher mixing of the rest; one fixed sketch, set-up timed apart),
     Mc in {10, 5, 2}; with the network taken as the identity (the
-    operators' part) -- eagerly and as one HIP graph replayed per iteration
-    (fixed operators only) -- and with the residual BN U-Net (2 channels,
+    operators' part) -- eagerly and as one HIP graph replayed per iteration --
+    and with the residual BN U-Net (2 channels,
     widths 32-256) as F, adapted in full."""
     import torch
 
@@ -561,12 +561,16 @@ def mri_leg():
     # the same iteration (network = identity) captured once in a HIP graph and
     # replayed, for the fixed operators (the full one and the coil sketches)
     def run_graph(kind, mc):
-        o, ys = sketch_for(kind, mc)()
-        gs = mri.MRIGraphStep(prob.x0, ys, o)
-        return round(1e3 * mri.time_per_iteration(lambda: gs.step(rot[int(g.integers(360))].unsqueeze(0)),
-                                                   iters=50, warmup=5), 4)
-    out["identity_graph_ms_per_iteration"] = {f"{k}_Mc{mc}": run_graph(k, mc) for k, mc in cases
-                                              if k != "classical"}
+        if kind == "classical":
+            gs = mri.MRIGraphStep(prob.x0, y, op, select=mc)
+            step = lambda: gs.step(rot[int(g.integers(360))].unsqueeze(0),  # noqa: E731
+                                   g.choice(nc, size=mc, replace=False))
+        else:
+            o, ys = sketch_for(kind, mc)()
+            gs = mri.MRIGraphStep(prob.x0, ys, o)
+            step = lambda: gs.step(rot[int(g.integers(360))].unsqueeze(0))  # noqa: E731
+        return round(1e3 * mri.time_per_iteration(step, iters=50, warmup=5), 4)
+    out["identity_graph_ms_per_iteration"] = {f"{k}_Mc{mc}": run_graph(k, mc) for k, mc in cases}
     torch.manual_seed(0)
     base = ttt.ResUNet(width=32, depth=4, channels=2).to(dev)
     import copy

@@ -326,11 +326,20 @@ class MRIGraphStep:
     memset node.  x is updated in place."""
 
     def __init__(self, x0: torch.Tensor, y: torch.Tensor, op: MRIOperator, lam: float = 1.0, lr: float = 5e-4,
-                 warmup: int = 3):
+                 warmup: int = 3, select: int = 0):
+        """select > 0: the classical sketch, a new subset of `select` coils
+        per replay -- the selection matrix is a static device buffer (set by
+        step), and the sketched maps, data and weights are formed inside the
+        graph by the library's coil mixing."""
         self.x = x0.detach().clone().requires_grad_(True)
         self.y, self.op, self.lam = y, op, lam
         self.cs = torch.zeros((1, 2), device=x0.device, dtype=torch.float32)
         self.cs[0, 0] = 1.0
+        self.select = int(select)
+        if self.select:
+            G = np.zeros((self.select, op.nc))
+            G[np.arange(self.select), np.arange(self.select)] = 1.0
+            self.G = _dev_c64(G, x0.device)
         self.opt = torch.optim.Adam([self.x], lr=lr, capturable=True)
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
@@ -355,15 +364,28 @@ class MRIGraphStep:
 
     def _iteration(self):
         self.opt.zero_grad(set_to_none=True)
-        loss, _, _ = mri_ei_loss(self.x, self.y, self.op, self.cs, self.lam, library_sums=True)
+        if self.select:
+            op = MRIOperator(coil_mix_(self.G, self.op.maps), self.op.mask)
+            op.weights   # formed inside the graph from this replay's maps
+            y = coil_mix_(self.G, self.y)
+        else:
+            op, y = self.op, self.y
+        loss, _, _ = mri_ei_loss(self.x, y, op, self.cs, self.lam, library_sums=True)
         loss.backward()
         self.opt.step()
         return loss.detach()
 
-    def step(self, cos_sin: torch.Tensor):
-        """One iteration with the rotation cos_sin [1, 2]; returns the loss
-        (device scalar, valid after the stream reaches it)."""
+    def step(self, cos_sin: torch.Tensor, coils=None):
+        """One iteration with the rotation cos_sin [1, 2] (and, for the
+        classical sketch, the coil subset `coils`); returns the loss (device
+        scalar, valid once the stream reaches it)."""
         self.cs.copy_(cos_sin)
+        if self.select:
+            if coils is None or len(coils) != self.select:
+                raise ValueError(f"pass {self.select} coils")
+            G = np.zeros((self.select, self.op.nc), dtype=np.complex64)
+            G[np.arange(self.select), np.asarray(coils)] = 1.0
+            self.G.copy_(torch.from_numpy(G))
         self.graph.replay()
         return self.loss
 

@@ -76,3 +76,30 @@ def test_graph_replays_equal_eager_iterations(setup):
     loss = g.step(rot[seq[0]:seq[0] + 1])
     torch.cuda.synchronize()
     assert float(torch.max(torch.abs(g.x.detach() - eager[0][0]))) <= 1e-6 * float(torch.max(torch.abs(eager[0][0])))
+
+
+def test_classical_sketch_graph_equals_eager(setup):
+    mri, op, y, x0, rot = setup
+    subsets = [[1, 4, 6], [0, 7, 2], [5, 3, 1]]
+    seq = [30, 150, 270]
+    xe = x0.clone().requires_grad_(True)
+    opt = torch.optim.Adam([xe], lr=5e-4, capturable=True)
+    eager = []
+    for i, coils in zip(seq, subsets):
+        op_s, y_s = mri.classical_sketch(op, y, coils)
+        opt.zero_grad(set_to_none=True)
+        loss, _, _ = mri.mri_ei_loss(xe, y_s, op_s, rot[i:i + 1], 1.0, library_sums=True)
+        loss.backward()
+        opt.step()
+        eager.append((xe.detach().clone(), float(loss)))
+    g = mri.MRIGraphStep(x0, y, op, select=3)
+    for rep, (i, coils, (x_ref, l_ref)) in enumerate(zip(seq, subsets, eager)):
+        loss = g.step(rot[i:i + 1], coils)
+        torch.cuda.synchronize()
+        op.fwd_(x0)
+        torch.cuda.synchronize()
+        dx = float(torch.max(torch.abs(g.x.detach() - x_ref)) / torch.max(torch.abs(x_ref)))
+        dl = abs(float(loss) - l_ref) / l_ref
+        print(f"[mri-graph] classical replay {rep} coils {coils}: image {dx:.1e} loss {dl:.1e}", flush=True)
+        assert dx <= 1e-6 and dl <= 1e-9
+
