@@ -248,7 +248,10 @@ int ei_loss_grad_impl(const skei_geom *g, const float *x, const float *y, int ba
     const hipStream_t st = S(stream);
     const RayShape fwd_sh = merge_shapes(J.fwd_shape[0], J.fwd_shape[1]);
     if ((rc = staged(SKEI_STAGE_ROTATE, st, [&] { return rotate_run(inline_jobs(J.rot, 2), st); }))) return rc;
-    if ((rc = staged(SKEI_STAGE_FWD, st, [&] { return ray_run(kRayFwd, false, fwd_sh, inline_jobs(J.fwd, 2), st); })))
+    // the MC job's items (full scan, the residual's precise sums) are the
+    // longest: listed first, they start first and do not form the tail
+    const RayJob fwd_jobs[2] = {J.fwd[1], J.fwd[0]};
+    if ((rc = staged(SKEI_STAGE_FWD, st, [&] { return ray_run(kRayFwd, false, fwd_sh, inline_jobs(fwd_jobs, 2), st); })))
         return rc;
     if ((rc = staged(SKEI_STAGE_RAMP, st,
                      [&] { return ramp_run(false, ramp_block(g->n_det), ramp_shm(g->n_det), inline_jobs(J.ramp, 2), st); })))
@@ -270,7 +273,8 @@ int ei_loss_grad_impl(const skei_geom *g, const float *x, const float *y, int ba
                      [&] { return ramp_run(true, ramp_block(g->n_det), ramp_shm(g->n_det), inline_jobs(rampT, 2), st); })))
         return rc;
     if ((rc = staged(SKEI_STAGE_ADJ, st, [&] {
-             return gather_run(kGatherJosephAdj, gather_groups_auto(std::max(m, m_mc)), inline_jobs(J.adj, 2), st);
+             const GatherJob adj_jobs[2] = {J.adj[1], J.adj[0]};   // the full-scan MC items first
+             return gather_run(kGatherJosephAdj, gather_groups_auto(std::max(m, m_mc)), inline_jobs(adj_jobs, 2), st);
          })))
         return rc;
     return staged(SKEI_STAGE_ROTATE_ADJ, st, [&] { return rotate_adj_run(inline_jobs(&J.radj, 1), st); });

@@ -169,8 +169,8 @@ int plan_build(skei_ei_plan *P)
         if (bpt_c.waves == 0 && J.grad) bpt_c.waves = J.bpt_shape.waves;
         rot.push_back(J.rot[0]);
         rot.push_back(J.rot[1]);
+        fwd.push_back(J.fwd[1]);   // the full-scan MC job's long items first
         fwd.push_back(J.fwd[0]);
-        fwd.push_back(J.fwd[1]);
         for (int k = 0; k < 2; k++) {
             t[SKEI_STAGE_FWD].ray = merge_shapes(t[SKEI_STAGE_FWD].ray, J.fwd_shape[k]);
         }
@@ -184,8 +184,8 @@ int plan_build(skei_ei_plan *P)
             t[SKEI_STAGE_BP_T].ray = merge_shapes(t[SKEI_STAGE_BP_T].ray, J.bpt_shape);
             rampT.push_back(J.rampT);
             loss.push_back(make_loss_job(J.red));
+            adj.push_back(J.adj[1]);   // the full-scan MC job's long items first
             adj.push_back(J.adj[0]);
-            adj.push_back(J.adj[1]);
             max_m_adj = std::max(max_m_adj, std::max(p.m, p.m_mc));
             if (P->tuning) {   // timing runs must not move the caller's image
                 J.radj.x_upd = nullptr;
