@@ -30,6 +30,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import statistics
 import sys
 import time
@@ -759,11 +760,23 @@ def traffic_for(stage, shape):
 RAY_KERNEL_SOURCES = ("k_project.hip", "skei_internal.h", "work.h", "geom.hip")
 
 
+_TOKENS = re.compile(r'"(?:\\.|[^"\\\n])*"|//[^\n]*|/\*.*?\*/', re.S)
+
+
+def code_text(src: str) -> str:
+    """The source with its comments dropped and whitespace runs folded to one
+    space (string literals are kept whole), so that a comment edit leaves the
+    fingerprint of the code unchanged."""
+    code = _TOKENS.sub(lambda m: m.group(0) if m.group(0).startswith('"') else " ", src)
+    return re.sub(r"\s+", " ", code).strip()
+
+
 def source_sha():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2411_05771_amd", "csrc")
     for f in RAY_KERNEL_SOURCES:
-        h.update(open(os.path.join(csrc, f), "rb").read())
+        with open(os.path.join(csrc, f)) as fh:
+            h.update(code_text(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

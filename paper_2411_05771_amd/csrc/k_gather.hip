@@ -277,9 +277,13 @@ __device__ __forceinline__ void gather_item(const GatherJob &J, long long item)
 // registers that spill are the staging pass's, and the occupancy gained hides
 // the staging latency (measured on MI355X: Joseph adjoint and backprojection
 // of 16 images of 256^2 over 90 angles in 62 and 41 us, against 69 and 48 us
-// at the unconstrained 98 VGPRs)
+// at the unconstrained 98 VGPRs).  One- and two-group workgroups of one
+// pixel per thread are held to seven waves (72 VGPRs, 24 bytes spilled for one
+// group): there few listed angles leave each item short and latency-bound
+// (measured on MI355X: a 512^2 image with 16 copies over 5 listed angles, the
+// backprojection and the Joseph adjoint 45.4 -> 42.8 and 48.6 -> 41.3 us)
 template <int KIND, int GA, int PPT>
-__global__ void __launch_bounds__(256 * GA / PPT) __attribute__((amdgpu_waves_per_eu(GA == 4 ? 8 : 1))) k_gather(const JobList<GatherJob> L)
+__global__ void __launch_bounds__(256 * GA / PPT) __attribute__((amdgpu_waves_per_eu(GA == 4 ? 8 : PPT == 1 ? 7 : 1))) k_gather(const JobList<GatherJob> L)
 {
     for_each_item(L, [&](const GatherJob &J, long long item) { gather_item<KIND, GA, PPT>(J, item); });
 }
@@ -359,11 +363,14 @@ void gather_lds_reads(int n, long long out[3])
     out[2] = WIN;
 }
 
-// Default gather shape for up to m listed angles: four angle groups with four
-// pixels per thread once there are enough angles to share, else one of each
-// (measured on MI355X, the 512^2 EI step with 16 copies of 50 listed angles:
-// 674 -> 595 us with four groups from 8 angles up instead of 64).
-int gather_groups_auto(int m) { return m >= 8 ? 44 : 1; }
+// Default gather shape for up to m listed angles: one angle group of one pixel
+// per thread while few angles leave each item latency-bound, two groups of
+// four pixels per thread in between, four groups once there are enough angles
+// to share (measured on MI355X, a 512^2 image with 16 copies: backprojection /
+// Joseph adjoint at 10 angles 48.3 / 48.2 us with one group against 54.6 /
+// 51.4 with four; at 20 angles 59.0 / 58.7 with two against 60.9 / 59.5; at
+// 50 angles 91.0 / 96.8 with four against 95.3 / 102.7 with two).
+int gather_groups_auto(int m) { return m < 12 ? 1 : m < 32 ? 24 : 44; }
 
 size_t gather_items(int n, int batch)
 {

@@ -479,14 +479,17 @@ __device__ __forceinline__ void ray_item(const RayJob &J, long long item, float 
                     const int ub = max(ulo[0], M0), ue = min(whi, M0 + Rc - 1);
                     if (resid) {
                         // residual jobs: each line's lerp in float, four lines
-                        // (aligned) summed in float, then added in double; a
-                        // unit's groups are unrolled (measured on MI355X: the
-                        // headline forward 70.2 -> 67.6 us, one spilled VGPR)
+                        // (aligned) summed in float, then added in double; the
+                        // groups stay rolled: unrolled, the forward launch of
+                        // one 512^2 image sketched to 5 or 10 angles (whose few
+                        // residual items set its length) measured 81 -> 102 us
+                        // on MI355X, with no gain at the 16-copy 256^2 step
+                        // (traced 65.4 unrolled against 64.5 us)
 #pragma unroll 1
                         for (int Mb = ub; Mb <= ue; Mb += U) {
                             // entry j of line Mb + l sits at index j + kBias of `line`
                             const float *ubase = chunk + (Mb - M0) * pitch + kLinePad - kBias;
-#pragma unroll
+#pragma unroll 1
                             for (int l4 = 0; l4 < U; l4 += 4) {
                                 float v4[RPT];
 #pragma unroll
