@@ -161,9 +161,9 @@ int ei_problem_jobs(const skei_ei_problem &p, const EiBuffers &b, const RayChoic
     // Without a tuning of the geometry, the ray jobs take the plans' default
     // rays per thread (one angle per item for N_det up to the slots): items
     // holding several angles measured markedly slower than one-angle items.
-    const int def_rpt = g->n_det > 400 ? 3 : 2;
-    const int rpt_f = fwd.own && tf.group == 0 && tf.split == 0 ? def_rpt : fwd.rpt;
-    const int rpt_b = bpt.own && tb.group == 0 && tb.split == 0 ? def_rpt : bpt.rpt;
+    const long long rows_f = (long long)bc * m + (long long)batch * m_mc, rows_b = (long long)bc * m;
+    const int rpt_f = fwd.own && tf.group == 0 && tf.split == 0 ? ray_rpt_default(g->n_det, rows_f, false) : fwd.rpt;
+    const int rpt_b = bpt.own && tb.group == 0 && tb.split == 0 ? ray_rpt_default(g->n_det, rows_b, true) : bpt.rpt;
     if ((rc = make_ray_job(g, b.z, b.zT, bc, p.angle_idx, m, b.ys, nullptr, tf, rpt_f, J.fwd[0],
                            J.fwd_shape[0])))
         return rc;

@@ -52,6 +52,11 @@ struct RayChoice {
 int ei_problem_jobs(const skei_ei_problem &p, const EiBuffers &b, const RayChoice &fwd, const RayChoice &bpt,
                     EiJobs &J);
 
+// Default rays-per-thread cap of an EI ray launch over `rows` (image, listed
+// angle) pairs: 3 for rows wider than 400 detectors, else 2; fewer when the
+// launch has too few rows to fill the chip (transpose: the B^T stage).
+int ray_rpt_default(int n_det, long long rows, bool transpose);
+
 // Stage probe (skei_probe_set): events around the launch of one stage.
 int probe_begin(int stage, hipStream_t st);
 int probe_end(int stage, hipStream_t st);

@@ -126,21 +126,41 @@ struct skei_ei_plan {
     bool tuning = false;           // while true the fused x -= step * grad is left out
 };
 
+// One angle per item fills a workgroup with up to 3 x 256 rays; below 256 rows
+// (512 for B^T) a launch of such items leaves most CUs idle, and splitting
+// each row over more workgroups wins (measured on MI355X, a 512^2 image with
+// 16 copies, 726 detectors, per stage: forward / B^T at 5 angles 81.0 / 100.5
+// -> 66.6 / 64.2 us with one ray per thread; at 20 angles the forward is best
+// at two rays, 89.0 -> 80.9 us, and B^T at one, 107.8 -> 83.8 us; from 50
+// angles up the three-ray default is best)
+int skei::ray_rpt_default(int n_det, long long rows, bool transpose)
+{
+    const int def = n_det > 400 ? 3 : 2;
+    if (rows < 256 || (transpose && rows < 512)) return 1;
+    if (rows < 512) return std::min(def, 2);
+    return def;
+}
+
 namespace {
 
 int plan_build(skei_ei_plan *P)
 {
     // default rays per thread: 2 fills a workgroup with one angle of up to
-    // 512 detectors; wider detector rows pack better at 3
+    // 512 detectors; wider detector rows pack better at 3; launches with few
+    // (image, angle) rows take fewer (ray_rpt_default)
     int max_nd = 1;
-    for (const skei_ei_problem &p : P->probs) max_nd = std::max(max_nd, p.geom->n_det);
-    const int def_rpt = max_nd > 400 ? 3 : 2;
+    long long rows_f = 0, rows_b = 0;
+    for (const skei_ei_problem &p : P->probs) {
+        max_nd = std::max(max_nd, p.geom->n_det);
+        rows_f += (long long)p.batch * p.copies * p.m + (long long)p.batch * p.m_mc;
+        if (p.grad) rows_b += (long long)p.batch * p.copies * p.m;
+    }
     // ray-stage shape code: rays per thread + 100 x march unit height, + 10000
     // for three-wave workgroups, + 20000 for LDS chunks of four units, + 40000
     // for six-wave and + 80000 for eight-wave workgroups (both run best with
     // the higher occupancy of 8-line chunks by default; the default wave
     // count is the first problem's automatic choice)
-    auto choice = [&](int shape, int def_lines) {
+    auto choice = [&](int shape, int def_lines, int def_rpt) {
         RayChoice c;
         c.own = false;
         c.rpt = shape % 100 > 0 ? shape % 100 : def_rpt;
@@ -149,8 +169,8 @@ int plan_build(skei_ei_plan *P)
         c.units = ray_code_units4(shape) ? 4 : 2;
         return c;
     };
-    RayChoice fwd_c = choice(P->cfg[SKEI_STAGE_FWD].shape, 8);
-    RayChoice bpt_c = choice(P->cfg[SKEI_STAGE_BP_T].shape, 8);
+    RayChoice fwd_c = choice(P->cfg[SKEI_STAGE_FWD].shape, 8, ray_rpt_default(max_nd, rows_f, false));
+    RayChoice bpt_c = choice(P->cfg[SKEI_STAGE_BP_T].shape, 8, ray_rpt_default(max_nd, rows_b, true));
     std::vector<RotJob> rot;
     std::vector<RayJob> fwd, bpt;
     std::vector<RampJob> ramp, rampT, loss;
