@@ -669,12 +669,18 @@ def batched_leg(args):
         percall()
     plan_ms, _ = timed_steps(plan.run, reps, -1)
     call_ms, _ = timed_steps(percall, reps, -1)
+    stages = probe_stages(plan.run, reps=3)
     rays = sum(2.0 * (p["n_angles"] + p["copies"] * p["m"]) * p["n_det"] for p in specs)
+    # a ray marches N image lines, so rays of the 512^2 problems cost twice those
+    # of 256^2: ray-lines per second compare workloads of different sizes
+    ray_lines = sum(2.0 * (p["n_angles"] + p["copies"] * p["m"]) * p["n_det"] * p["n"] for p in specs)
     plan.close()
     return {"workload": "uneven_64_problems_8copies", "problems": len(specs), "plan_ms": round(plan_ms, 4),
             "per_problem_calls_ms": round(call_ms, 4), "speedup": round(call_ms / plan_ms, 3),
-            "plan_grays": round(rays / (plan_ms * 1e-3) / 1e9, 4), "launches_per_step": {"plan": 8,
-                                                                                        "per_problem": 8 * len(specs)}}
+            "plan_grays": round(rays / (plan_ms * 1e-3) / 1e9, 4),
+            "plan_g_ray_lines_per_s": round(ray_lines / (plan_ms * 1e-3) / 1e9, 1),
+            "plan_stage_ms": {k: round(v, 3) for k, v in stages.items()},
+            "launches_per_step": {"plan": 8, "per_problem": 8 * len(specs)}}
 
 
 def serving_sweep(specs_at, rates, budget, executors, label):
