@@ -74,3 +74,28 @@ def test_autograd_matches_fused_step(skei, orc):
     assert abs(loss.item() - want_l) < 1e-5 * want_l
     assert relerr(host(x.grad), host(g2)) < 1e-5
     assert relerr(host(x.grad), want_g) < 1e-5
+
+
+@pytest.mark.parametrize("split", [20, 5], ids=["paper512_N20", "paper512_N5"])
+def test_paper_geometry_sketch_matches_oracle(skei, orc, split):
+    """The paper's CT geometry (Sec. 4.1.1: 512^2, 100 angles, 726 detectors)
+    with 16 copies and the interleaved sketch S_0 of an N-way split (Sec.
+    4.2.1) as both the EI and the MC angle list.  With 5 or 20 listed angles
+    the launches hold few (image, angle) rows, so the ray stages take one or
+    two rays per thread and the gathers one or two angle groups."""
+    from paper_2411_05771_amd import ei
+    n, na, nd, copies = 512, 100, 726, 16
+    x0, y, _, cs = workload(orc, n, na, nd, 1, copies, 1)
+    idx = synth.interleaved_sketch(na, split, 0)
+    print(f"\n[ei] paper geometry n={n} n_angles={na} n_det={nd} copies={copies} N={split} m={len(idx)}", flush=True)
+    want_l, want_g = orc.ei_loss_grad(x0, y, na, idx, cs, 1.0, mc_idx=idx)
+    geom = skei.Geometry(n, na, nd)
+    sk = geom.sketch(idx)
+    step = ei.EIStep(geom, to_dev(y), sk, to_dev(cs), 1.0, mc=sk)
+    loss, grad = step(to_dev(x0))
+    got_l = float(loss.item())
+    e_l = abs(got_l - want_l) / abs(want_l)
+    e_g = relerr(host(grad), want_g)
+    print(f"[ei] loss {got_l:.9e} vs {want_l:.9e} rel {e_l:.2e}; grad relerr {e_g:.2e}", flush=True)
+    assert e_l < 1e-5
+    assert e_g < 1e-5
