@@ -88,18 +88,20 @@ int make_ray_job(const skei_geom *g, const float *x, const float *xT, int batch,
     const long long base_items = (long long)batch * m;
     // A launch of a few rows (one image sketched to a few angles) is as long
     // as one item's march over every image line: one angle per item and rows
-    // cut into segments of ~60 detectors put more workgroups on that march
-    // (measured on MI355X, the forward of one 512^2 image, 726 detectors:
-    // 100.6 -> 62.4 us at 5 angles and 101.6 -> 62.9 us at 10 with 12
-    // segments; at 100 angles the two-segment default stays)
-    const bool few = rpt_cap == 0 && t.split == 0 && t.group == 0 && base_items <= 32 && nd >= 128;
+    // cut into segments of ~60 detectors put more workgroups on that march,
+    // up to ~640 items (measured on MI355X, the forward of one image: 512^2,
+    // 726 detectors, 12 segments, 100.6 -> 62.4 us at 5 angles, 102.6 ->
+    // 75.5 us at 50, slower at 100; 256^2, 363 detectors, 6 segments, 75.3 ->
+    // 35.9 us at 36 angles and 75.7 -> 45.0 us at 72, slower at 360)
+    const int few_seg = std::min(16, nd / 60);
+    const bool few = rpt_cap == 0 && t.split == 0 && t.group == 0 && nd >= 300 && base_items * few_seg <= 640;
     // listed angles per item (G) and detector segments (nseg) for workgroups
     // of `w` waves; returns the fraction of ray slots that hold a ray
     auto layout = [&](int w, int &G, int &nseg) {
         const int block = 64 * w;
         const int cap = (rpt_cap > 0 ? std::min(rpt_cap, kMaxRpt) : kMaxRpt) * block;
         nseg = t.split > 0 ? t.split
-               : few       ? std::min(16, nd / 60)
+               : few       ? few_seg
                : rpt_cap > 0 ? (nd + cap - 1) / cap : ((base_items < 512 && nd >= 128) ? 2 : 1);
         nseg = std::max(1, std::min(nseg, nd));
         G = t.group > 0 ? t.group
